@@ -18,19 +18,18 @@
 /* Incremental-stencil WENO reconstruction, Sec. 3.3                          */
 /* ------------------------------------------------------------------------ */
 
-/* Candidate values at x_{i+1/2}, eq. (20), on v = (q_{i-2},...,q_{i+2}).
- * Stencils follow Fig. 1: S1 = {i,i+1}, S2 = {i-1,i}, S3 = {i,i+1,i+2},
- * S4 = {i-2,i-1,i}.  The first candidate is printed with a minus sign; the
- * sign that makes it a consistent 2-point reconstruction (coefficients
- * summing to one, and the linear combination with d_k equal to the
- * 5th-order upwind scheme) is a plus: q1 = (q_i + q_{i+1})/2.  The
- * coefficients are written over a common denominator. */
+/* Candidate values at x_{i+1/2}, eq. (20), on v = (q_{i-2},...,q_{i+2}),
+ * with the printed coefficients.  Stencils follow Fig. 1: S1 = {i,i+1},
+ * S2 = {i-1,i}, S3 = {i,i+1,i+2}, S4 = {i-2,i-1,i}.  The first candidate is
+ * printed with a minus sign; the sign that makes it a consistent 2-point
+ * reconstruction (coefficients summing to one, and the linear combination
+ * with d_k equal to the 5th-order upwind scheme) is a plus. */
 void or_weno_candidates(const double v[5], double cand[4]) {
   const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
-  cand[0] = (c + d) / 2.0;
-  cand[1] = (3.0 * c - b) / 2.0;
-  cand[2] = (2.0 * c + 5.0 * d - e) / 6.0;
-  cand[3] = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  cand[0] = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+  cand[1] = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+  cand[2] = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+  cand[3] = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
 }
 
 /* Smoothness indicators beta_1..beta_4 (eq. (24)), beta_12 of the central

@@ -96,7 +96,7 @@ def test_candidates_are_polynomial_reconstructions():
         cand = oracle.weno_candidates(v)
         for k, cells in STENCILS.items():
             exact = poly_eval(fit_poly(cells, [v[j + 2] for j in cells]), Fr(1, 2))
-            assert cand[k] == pytest.approx(float(exact), rel=1e-15, abs=1e-13)
+            assert cand[k] == pytest.approx(float(exact), rel=1e-14, abs=1e-12)
 
 
 def test_linear_weights_give_fifth_order_upwind_scheme():
@@ -130,7 +130,7 @@ def test_tau5_zero_reproduces_linear_scheme(weights):
         w = oracle.weno_weights(v, weights)
         np.testing.assert_allclose(w, [0.4, 0.2, 0.3, 0.1], rtol=1e-15)
         exact = 12 * (a2 * Fr(1, 4) + a1 * Fr(1, 2) + a0)
-        assert oracle.weno_is(v, weights) == pytest.approx(float(exact), rel=2e-15, abs=1e-13)
+        assert oracle.weno_is(v, weights) == pytest.approx(float(exact), rel=1e-14, abs=1e-12)
 
 
 def test_order3_with_linear_weights_is_third_order_scheme():
@@ -144,7 +144,7 @@ def test_order3_with_linear_weights_is_third_order_scheme():
         w = oracle.weno_weights(v, oracle.W_MODIFIED, order=3)
         np.testing.assert_allclose(w, [2 / 3, 1 / 3, 0, 0], rtol=1e-15, atol=0)
         central = poly_eval(fit_poly([-1, 0, 1], avgs[1:4]), Fr(1, 2))
-        assert oracle.weno_is(v, order=3) == pytest.approx(float(central), rel=2e-15, abs=1e-13)
+        assert oracle.weno_is(v, order=3) == pytest.approx(float(central), rel=1e-14, abs=1e-12)
 
 
 # ---------------------------------------------------------------- indicators
