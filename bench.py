@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput of the WENO-IS finite-volume RK3 stage on one MI355X.
+
+Workload: the 2D shock-bubble problem at 1024 x 512 cells (air cylinder in
+water hit by a 1 GPa water shock; workloads.shock_bubble_2d), MOOD on,
+CFL 0.5 time step recomputed on the device every step.  A step is one full
+RK3 step: the time-step reduction plus three stages, each stage a complete
+evaluation of the hot path (primitive recovery, characteristic projection,
+WENO-IS, MOOD cascade, HLLC, flux difference, Runge-Kutta update) over the
+whole grid.
+
+Metric: cell-updates per second per RK stage = cells * 3 * steps / time,
+inputs resident in HBM before the timed region.  `value` is the plain FP64
+path; the FP32 reconstruction/flux form is timed the same way and reported
+with its L1 difference from the FP64 path after the same steps.
+
+Printed: ONE JSON line (rank 0).  --gpus > 1 is refused: this build runs on
+a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+# Algorithmic floating-point operations (add, mul, div, sqrt, min/max each
+# one) of the method per face and per cell, counted from the operation
+# sequence of the paper's steps ("Algorithmic work"):
+#   face: averaged state and eigen-parameters 19, projection of six cells 48,
+#   WENO-IS 104 per field and side (2*nc reconstructions), back-projection
+#   16, positivity tests 6, HLLC 103 + 8 per transverse velocity;
+#   cell, per axis: flux difference and material source 3*nc + 6 ... (below)
+FACE_FLOPS = {1: 19 + 48 + 104 * 10 + 16 + 6 + 103,
+              2: 19 + 48 + 104 * 12 + 16 + 6 + 111,
+              3: 19 + 48 + 104 * 14 + 16 + 6 + 119}
+PRIM_FLOPS = {1: 9, 2: 12, 3: 15}          # primitive recovery per cell
+AXIS_CELL_FLOPS = {1: 16, 2: 18, 3: 20}    # flux difference + source per cell and axis
+ACC_FLOPS = {1: 0, 2: 6, 3: 7}             # summing the axes' contributions
+RK_FLOPS = {1: 3 * 5, 2: 4 * 6, 3: 4 * 7}  # stage update per cell (stage-average)
+# Algorithmic HBM bytes per cell and stage: read U_s and write U_{s+1}
+# (8 bytes x nc each), plus U^n in stages 2 and 3 (2/3 on average).
+def BYTES_PER_CELL_STAGE(nd):
+    nc = 4 + nd
+    return 8 * nc * (2 + 2 / 3)
+
+
+PEAK = {"f64_valu_tflops": 78.6, "f32_valu_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 512 MiB device copy (reference for HBM counters)")
+    return ap.parse_args()
+
+
+def run_form(isweno, ctx, p, U0, opts, steps, warmup, torch):
+    grid = isweno.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    U = U0.clone()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = isweno.new_stats()
+    for _ in range(warmup):
+        ctx.rk3_step(U, grid, opts, dt, st)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.rk3_step(U, grid, opts, dt, st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern = {}
+    for k, name in isweno.K_NAMES.items():
+        ms, n = ctx.timing_read(k)
+        if n:
+            kern[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n}
+    ctx.timing_enable(False)
+    stats = isweno.read_stats(st)
+    return U, el, kern, stats
+
+
+def roofline(kern, p, precision):
+    """Dominant kernel's achieved FLOP rate against the vector-ALU peak."""
+    nd = p.ndim
+    name, k = max(((n, v) for n, v in kern.items() if n.startswith("sweep")),
+                  key=lambda kv: kv[1]["total_ms"])
+    D = {"sweep_x": 0, "sweep_y": 1, "sweep_z": 2}[name]
+    faces = p.ncells // p.n[D] * (p.n[D] + 1)
+    cells = p.ncells
+    flops = faces * FACE_FLOPS[nd] + cells * (PRIM_FLOPS[nd] + AXIS_CELL_FLOPS[nd] + ACC_FLOPS[nd])
+    if D == nd - 1:
+        flops += cells * RK_FLOPS[nd]
+    achieved = flops / (k["avg_ms"] * 1e-3) / 1e12
+    peak = PEAK["f64_valu_tflops"] if precision == "f64" else PEAK["f32_valu_tflops"]
+    return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "flops_per_launch": int(flops), "avg_launch_ms": round(k["avg_ms"], 4)}
+
+
+def cpu_baseline(p, seconds):
+    """The oracle (plain FP64 C, OpenMP) on the same workload, first RK3
+    steps until about `seconds` of CPU work."""
+    import oracle
+    g = oracle.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    o = oracle.make_opts(mood=True, cfl=0.5)
+    U = p.U.copy()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        h = oracle.cfl_dt(U, g, o)
+        U, s = oracle.rk3_step(U, g, h, o)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": p.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
+            "cores": cores, "kind": "oracle",
+            "sample": f"first {steps} RK3 steps of the {p.n[0]}x{p.n[1]} shock-bubble "
+                      f"({steps * 3 * p.ncells} cell-stages, {el:.1f} s)"}
+
+
+def rel_l1(a, b):
+    return float((a - b).abs().sum() / b.abs().sum())
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    from paper_1707_00592_amd import isweno, workloads
+    isweno.load()
+    p = workloads.shock_bubble_2d(args.nx, args.ny)
+    U0 = torch.from_numpy(p.U).to("cuda")
+    ctx = isweno.Context(0)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = {}
+    for f in forms:
+        prec = isweno.FP32 if f == "fp32" else isweno.FP64
+        opts = isweno.make_opts(precision=prec, mood=True, cfl=0.5)
+        U, el, kern, st = run_form(isweno, ctx, p, U0, opts, args.steps, args.warmup, torch)
+        results[f] = {"U": U, "elapsed": el, "kern": kern, "stats": st}
+    base = results["fp64"]
+    cells_stages = p.ncells * 3 * args.steps
+    value = cells_stages / base["elapsed"]
+    out = {
+        "metric": "cell-updates/s per RK stage",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": base["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D shock-bubble {p.n[0]}x{p.n[1]}, FP64, MOOD on, CFL 0.5",
+                   "cells": p.ncells, "rk_stages_per_step": 3, "parallelism": "single GPU"},
+        "roofline": roofline(base["kern"], p, "f64"),
+        "kernels": base["kern"],
+        "mood": {"o3": list(base["stats"].o3[:2]), "o1": list(base["stats"].o1[:2]),
+                 "status": base["stats"].status},
+    }
+    rho64 = base["U"][0]
+    forms_out = {}
+    for f, r in results.items():
+        if f == "fp64":
+            continue
+        v = cells_stages / r["elapsed"]
+        forms_out[f] = {"value": v, "speedup_vs_fp64": v / value,
+                        "l1_rel_rho_vs_fp64": rel_l1(r["U"][0], rho64),
+                        "l1_rel_E_vs_fp64": rel_l1(r["U"][3], base["U"][3]),
+                        "status": r["stats"].status,
+                        "roofline": roofline(r["kern"], p, "f32")}
+    out["forms"] = forms_out
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per
+        # dispatch scale the counters of the stage kernels to bytes
+        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

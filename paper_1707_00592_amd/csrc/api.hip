@@ -1,0 +1,300 @@
+// C ABI of the WENO-IS library (declarations and contracts in isweno.h).
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <vector>
+
+#include "isweno.h"
+#include "launch.hpp"
+#include "sweep.hpp"
+
+struct isweno_ctx {
+  int device = 0;
+  int ncu = 256;
+  double* ws = nullptr;          // two state-sized buffers (U1, U2)
+  size_t ws_bytes = 0;
+  double* partial = nullptr;     // time-step reduction partials
+  static constexpr int kPartial = 4096;
+  // kernel timing
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double total_ms[ISWENO_K_COUNT] = {};
+  int64_t launches[ISWENO_K_COUNT] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(isweno_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct KTimer {
+  isweno_ctx* c;
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  KTimer(isweno_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+    if (c && c->timing) {
+      a = take_event(c);
+      if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    }
+  }
+  ~KTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      c->recs.push_back({kind, a, b});
+    } else {
+      c->pool.push_back(a);
+      if (b) c->pool.push_back(b);
+    }
+  }
+};
+
+void drain_timing(isweno_ctx* c) {
+  for (auto& r : c->recs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->total_ms[r.kind] += ms;
+      c->launches[r.kind] += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+}
+
+}  // namespace
+
+namespace {
+
+int check_grid(const isweno_grid* g) {
+  if (!g || g->ndim < 1 || g->ndim > 3 || g->reserved != 0) return ISWENO_ERR_ARG;
+  for (int d = 0; d < 3; d++) {
+    if (d < g->ndim) {
+      if (g->n[d] < 1 || !(g->dx[d] > 0.0)) return ISWENO_ERR_ARG;
+      if (g->bc_lo[d] < 0 || g->bc_lo[d] > 2 || g->bc_hi[d] < 0 || g->bc_hi[d] > 2)
+        return ISWENO_ERR_ARG;
+      if ((g->bc_lo[d] == ISWENO_BC_REFLECTIVE || g->bc_hi[d] == ISWENO_BC_REFLECTIVE) &&
+          g->n[d] < 3)
+        return ISWENO_ERR_ARG;
+    } else if (g->n[d] != 1) {
+      return ISWENO_ERR_ARG;
+    }
+  }
+  const int64_t N = g->n[0] * g->n[1] * g->n[2];
+  if (N / g->n[0] / g->n[1] != g->n[2]) return ISWENO_ERR_ARG;  // overflow
+  return ISWENO_OK;
+}
+
+int check_opts(const isweno_opts* o) {
+  if (!o || o->reserved != 0 || o->reserved2 != 0) return ISWENO_ERR_ARG;
+  if (o->precision != ISWENO_FP64 && o->precision != ISWENO_FP32) return ISWENO_ERR_ARG;
+  if (o->weights < 0 || o->weights > 2) return ISWENO_ERR_ARG;
+  if (o->mood != 0 && o->mood != 1) return ISWENO_ERR_ARG;
+  if (!(o->eps >= 0.0)) return ISWENO_ERR_ARG;
+  if (o->weights == ISWENO_W_MLP) {
+    // the learned weights run with the float32 reconstruction only
+    if (!o->mlp_params) return ISWENO_ERR_ARG;
+    if (o->precision != ISWENO_FP32) return ISWENO_ERR_UNSUPPORTED;
+  }
+  return ISWENO_OK;
+}
+
+int64_t ncells(const isweno_grid* g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+int ensure_ws(isweno_ctx* c, size_t bytes) {
+  if (c->ws_bytes >= bytes) return ISWENO_OK;
+  if (c->ws) {
+    // the old buffers may still be in use by queued work on any stream
+    if (hipDeviceSynchronize() != hipSuccess) return ISWENO_ERR_DEVICE;
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  if (hipMalloc(&c->ws, bytes) != hipSuccess) return ISWENO_ERR_DEVICE;
+  c->ws_bytes = bytes;
+  return ISWENO_OK;
+}
+
+isw::SweepArgs base_args(const isweno_grid* g, const isweno_opts* o, isweno_stats* st) {
+  isw::SweepArgs a{};
+  for (int d = 0; d < 3; d++) {
+    a.n[d] = g->n[d];
+    a.dx[d] = g->dx[d];
+  }
+  a.weights = o->weights;
+  a.mood = o->mood;
+  a.eps = o->eps;
+  a.stats = reinterpret_cast<isw::StatsDev*>(st);
+  a.mlp = o->mlp_params;
+  a.mlp_thr = o->mlp_conf_threshold;
+  return a;
+}
+
+// One evaluation of L on Uin followed by the output step `mode`; the partial
+// sums of the first ndim-1 axes go to `partial` (which may alias the final
+// output buffer, cell by cell).
+hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw::SweepArgs a,
+                 double* partial, int mode, hipStream_t s) {
+  const int nd = g->ndim;
+  for (int D = 0; D < nd; D++) {
+    isw::SweepArgs b = a;
+    b.bc_lo = g->bc_lo[D];
+    b.bc_hi = g->bc_hi[D];
+    const bool last = D == nd - 1;
+    b.R = partial;
+    if (!last) b.Rout = partial;
+    KTimer t(c, ISWENO_K_SWEEP_X + D, s);
+    const hipError_t e =
+        isw::launch_sweep(o->precision, nd, D, b, last ? mode : isw::OUT_PARTIAL, D > 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* isweno_version(void) { return "isweno 0.1 (gfx950)"; }
+
+int isweno_create(isweno_ctx** out, int device) {
+  if (!out) return ISWENO_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return ISWENO_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return ISWENO_ERR_DEVICE;
+  isweno_ctx* c = new (std::nothrow) isweno_ctx();
+  if (!c) return ISWENO_ERR_DEVICE;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->ncu = prop.multiProcessorCount;
+  if (hipMalloc(&c->partial, sizeof(double) * isweno_ctx::kPartial) != hipSuccess) {
+    delete c;
+    return ISWENO_ERR_DEVICE;
+  }
+  *out = c;
+  return ISWENO_OK;
+}
+
+void isweno_destroy(isweno_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->partial) (void)hipFree(c->partial);
+  drain_timing(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int isweno_rhs(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, const double* U,
+               double* dUdt, isweno_stats* stats, void* stream) {
+  int r;
+  if (!c || !U || !dUdt) return ISWENO_ERR_ARG;
+  if ((r = check_grid(g)) != ISWENO_OK) return r;
+  if ((r = check_opts(o)) != ISWENO_OK) return r;
+  const int64_t N = ncells(g);
+  const int nc = 4 + g->ndim;
+  if ((U < dUdt + (size_t)nc * N) && (dUdt < U + (size_t)nc * N)) return ISWENO_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  isw::SweepArgs a = base_args(g, o, stats);
+  a.Uin = U;
+  a.Rout = dUdt;
+  return stage(c, g, o, a, dUdt, isw::OUT_RHS, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
+}
+
+int isweno_cfl_dt(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, const double* U,
+                  double* dt, void* stream) {
+  int r;
+  if (!c || !U || !dt) return ISWENO_ERR_ARG;
+  if ((r = check_grid(g)) != ISWENO_OK) return r;
+  if (!o || !(o->cfl > 0.0)) return ISWENO_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  KTimer t(c, ISWENO_K_CFL, s);
+  return isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->partial,
+                         isweno_ctx::kPartial, dt, c->ncu,
+                         s) == hipSuccess
+             ? ISWENO_OK
+             : ISWENO_ERR_DEVICE;
+}
+
+int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
+                    double* dt, isweno_stats* stats, void* stream) {
+  int r;
+  if (!c || !U || !dt) return ISWENO_ERR_ARG;
+  if ((r = check_grid(g)) != ISWENO_OK) return r;
+  if ((r = check_opts(o)) != ISWENO_OK) return r;
+  if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
+  const int64_t N = ncells(g);
+  const int nc = 4 + g->ndim;
+  const size_t sz = (size_t)nc * (size_t)N;
+  if ((r = ensure_ws(c, 2 * sz * sizeof(double))) != ISWENO_OK) return r;
+  double* U1 = c->ws;
+  double* U2 = c->ws + sz;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (o->cfl > 0.0) {
+    KTimer t(c, ISWENO_K_CFL, s);
+    if (isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->partial,
+                         isweno_ctx::kPartial, dt, c->ncu, s) !=
+        hipSuccess)
+      return ISWENO_ERR_DEVICE;
+  }
+  isw::SweepArgs a = base_args(g, o, stats);
+  a.dt = dt;
+  a.U0 = U;
+  // stage 1: U1 = U + dt L(U)
+  a.Uin = U;
+  a.Uout = U1;
+  if (stage(c, g, o, a, U1, isw::OUT_RK1, s) != hipSuccess) return ISWENO_ERR_DEVICE;
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+  a.Uin = U1;
+  a.Uout = U2;
+  if (stage(c, g, o, a, U2, isw::OUT_RK2, s) != hipSuccess) return ISWENO_ERR_DEVICE;
+  // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)); partial sums in U1
+  a.Uin = U2;
+  a.Uout = U;
+  if (stage(c, g, o, a, U1, isw::OUT_RK3, s) != hipSuccess) return ISWENO_ERR_DEVICE;
+  return ISWENO_OK;
+}
+
+int isweno_timing_enable(isweno_ctx* c, int enable) {
+  if (!c) return ISWENO_ERR_ARG;
+  drain_timing(c);
+  for (int k = 0; k < ISWENO_K_COUNT; k++) {
+    c->total_ms[k] = 0.0;
+    c->launches[k] = 0;
+  }
+  c->timing = enable != 0;
+  return ISWENO_OK;
+}
+
+int isweno_timing_read(isweno_ctx* c, int kind, double* total_ms, int64_t* launches) {
+  if (!c || kind < 0 || kind >= ISWENO_K_COUNT) return ISWENO_ERR_ARG;
+  drain_timing(c);
+  if (total_ms) *total_ms = c->total_ms[kind];
+  if (launches) *launches = c->launches[kind];
+  return ISWENO_OK;
+}
+
+// Batch and learned-weight entry points are provided in batch.hip / mlp.hip.
+
+}  // extern "C"

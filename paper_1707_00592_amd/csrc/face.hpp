@@ -1,0 +1,281 @@
+// Face-level device arithmetic of the WENO-IS finite-volume method
+// (arXiv:1707.00592): characteristic projection (Sec. 3.2, eqs. (11)-(13)),
+// WENO-IS reconstruction (Sec. 3.3, eqs. (19)-(29)), MOOD-type positivity
+// cascade (Sec. 3.4, eq. (32)) and the HLLC flux (Sec. 3.2.1,
+// eqs. (14)-(18)).
+//
+// Precision: the template type T is the arithmetic of the projection,
+// reconstruction and flux (double, or float for the mixed form).  The
+// back-projected face states and their positivity test are always double.
+// With T = double every operation is written in one fixed order (no fused
+// multiply-add; the library is compiled with -ffp-contract=off), so results
+// are reproducible bit for bit between launches and tile shapes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isw {
+
+// Optimal weights d_k of Sec. 3.3.1 and the 13/12 of the indicators.
+#define ISW_D1 0.4
+#define ISW_D2 0.2
+#define ISW_D3 0.3
+#define ISW_D4 0.1
+#define ISW_K13 (13.0 / 12.0)
+
+enum { W_MODIFIED = 0, W_BASIC = 1, W_MLP = 2 };
+
+template <typename T>
+__device__ __forceinline__ T dmin(T a, T b) { return a < b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
+
+// c^2 = gamma (p + Pinf) / rho of the stiffened gas (eq. (2)) in terms of
+// Gamma = 1/(gamma-1) and Pi = gamma Pinf/(gamma-1).
+template <typename T>
+__device__ __forceinline__ T sound2(T rho, T p, T G, T P) {
+  return ((G + T(1)) * p + P) / (G * rho);
+}
+
+// Admissibility used by the MOOD cascade: rho > 0, Gamma > 0 and
+// (Gamma+1) p + Pi > 0 (c^2 > 0, so every square root of the HLLC solver is
+// real and p + gamma Pinf > 0).
+__device__ __forceinline__ bool admissible(double rho, double p, double G,
+                                           double P) {
+  return (rho > 0.0) && (G > 0.0) && ((G + 1.0) * p + P > 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// WENO-IS on the left-biased stencil (a, b, c, d, e) = q~_{i-2..i+2}.
+// ---------------------------------------------------------------------------
+
+// Indicators of eqs. (24), (25) and the central beta_12 of Sec. 3.3.2.
+template <typename T>
+struct Ind {
+  T b1, b2, b3, b4, b12, tau;
+};
+
+template <typename T>
+__device__ __forceinline__ Ind<T> indicators(T a, T b, T c, T d, T e) {
+  const T k13 = T(ISW_K13);
+  Ind<T> r;
+  T t1, t2;
+  r.b1 = (d - c) * (d - c);
+  r.b2 = (c - b) * (c - b);
+  t1 = c - T(2) * d + e;
+  t2 = T(3) * c - T(4) * d + e;
+  r.b3 = k13 * t1 * t1 + T(0.25) * t2 * t2;
+  t1 = a - T(2) * b + c;
+  t2 = a - T(4) * b + T(3) * c;
+  r.b4 = k13 * t1 * t1 + T(0.25) * t2 * t2;
+  t1 = b - T(2) * c + d;
+  t2 = b - d;
+  r.b12 = k13 * t1 * t1 + T(0.25) * t2 * t2;
+  t1 = e - T(2) * d + T(2) * b - a;
+  t2 = e - T(4) * d + T(6) * c - T(4) * b + a;
+  r.tau = T(0.25) * t1 * t1 + k13 * t2 * t2;
+  return r;
+}
+
+// Unnormalised weights alpha_k: eq. (28) (modified) or eq. (21) with q = 1.
+// Order 3 drops the 3-point stencils (d3 = d4 = 0).
+struct Alpha {
+  double a1, a2, a3, a4;
+};
+
+__device__ __forceinline__ Alpha alphas_f64(const Ind<double>& s, int weights,
+                                            double eps, bool order3) {
+  Alpha al;
+  if (weights == W_BASIC) {
+    al.a1 = ISW_D1 * (1.0 + s.tau / (s.b1 + eps));
+    al.a2 = ISW_D2 * (1.0 + s.tau / (s.b2 + eps));
+    al.a3 = ISW_D3 * (1.0 + s.tau / (s.b3 + eps));
+    al.a4 = ISW_D4 * (1.0 + s.tau / (s.b4 + eps));
+  } else {
+    const double r12 = s.tau / (s.b12 + eps);
+    al.a1 = ISW_D1 * (1.0 + (s.tau / (s.b1 + eps)) * r12);
+    al.a2 = ISW_D2 * (1.0 + (s.tau / (s.b2 + eps)) * r12);
+    al.a3 = order3 ? 0.0 : ISW_D3 * (1.0 + s.tau / (s.b3 + eps));
+    al.a4 = order3 ? 0.0 : ISW_D4 * (1.0 + s.tau / (s.b4 + eps));
+  }
+  if (order3) {
+    al.a3 = 0.0;
+    al.a4 = 0.0;
+  }
+  return al;
+}
+
+// Eq. (19) in FP64: omega_k = alpha_k / sum(alpha), q = sum omega_k q^(k),
+// with the candidates of eq. (20) in their printed coefficients (the first
+// one read with a plus sign: (q_i + q_{i+1})/2).
+__device__ __forceinline__ double weno_f64(double a, double b, double c,
+                                           double d, double e, int weights,
+                                           double eps, bool order3) {
+  const Ind<double> s = indicators<double>(a, b, c, d, e);
+  const Alpha al = alphas_f64(s, weights, eps, order3);
+  const double sum = ((al.a1 + al.a2) + al.a3) + al.a4;
+  const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+  const double c2 = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+  if (order3) {
+    return (al.a1 / sum) * c1 + (al.a2 / sum) * c2;
+  }
+  const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+  const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+  return (((al.a1 / sum) * c1 + (al.a2 / sum) * c2) + (al.a3 / sum) * c3) +
+         (al.a4 / sum) * c4;
+}
+
+// Eq. (19) in FP32.  The indicators grow with the square of the data and
+// the modified weights multiply two ratios, which overflows float for the
+// pressure-like fields (|q| up to 1e9).  The stencil is therefore shifted by
+// its centre value and scaled by s = max |q_j - q_i| (both ratios of
+// eq. (28) are invariant under that map when epsilon is scaled by 1/s^2),
+// the scaled epsilon is kept >= 1e-30 and each product of ratios is clamped
+// at 1e30.  A stencil whose spread is below 1e-30 (flat, or denormal-level
+// noise such as a material property diffused into the other phase) returns
+// the centre value: its reciprocal would overflow float.
+__device__ __forceinline__ float weno_f32(float a, float b, float c, float d,
+                                          float e, int weights, float eps,
+                                          bool order3) {
+  const float s = fmaxf(fmaxf(fmaxf(fabsf(a - c), fabsf(b - c)), fabsf(d - c)),
+                        fabsf(e - c));
+  if (!(s > 1e-30f)) return c;
+  const float is = __builtin_amdgcn_rcpf(s);
+  const float A = (a - c) * is, B = (b - c) * is, D = (d - c) * is,
+              E = (e - c) * is;
+  const Ind<float> r = indicators<float>(A, B, 0.0f, D, E);
+  const float es = fmaxf(eps * is * is, 1e-30f);
+  float a1, a2, a3, a4;
+  if (weights == W_BASIC) {
+    a1 = 0.4f * (1.0f + r.tau * __builtin_amdgcn_rcpf(r.b1 + es));
+    a2 = 0.2f * (1.0f + r.tau * __builtin_amdgcn_rcpf(r.b2 + es));
+    a3 = 0.3f * (1.0f + r.tau * __builtin_amdgcn_rcpf(r.b3 + es));
+    a4 = 0.1f * (1.0f + r.tau * __builtin_amdgcn_rcpf(r.b4 + es));
+  } else {
+    const float r12 = r.tau * __builtin_amdgcn_rcpf(r.b12 + es);
+    a1 = 0.4f * (1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b1 + es) * r12, 1e30f));
+    a2 = 0.2f * (1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b2 + es) * r12, 1e30f));
+    a3 = 0.3f * (1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b3 + es), 1e30f));
+    a4 = 0.1f * (1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b4 + es), 1e30f));
+  }
+  const float C1 = 0.5f * D;
+  const float C2 = -0.5f * B;
+  if (order3) {
+    const float inv = __builtin_amdgcn_rcpf(a1 + a2);
+    return c + s * ((a1 * C1 + a2 * C2) * inv);
+  }
+  const float C3 = (5.0f * D - E) * (1.0f / 6.0f);
+  const float C4 = (2.0f * A - 7.0f * B) * (1.0f / 6.0f);
+  const float inv = __builtin_amdgcn_rcpf(((a1 + a2) + a3) + a4);
+  return c + s * ((a1 * C1 + a2 * C2 + a3 * C3 + a4 * C4) * inv);
+}
+
+template <typename T>
+__device__ __forceinline__ T weno(T a, T b, T c, T d, T e, int weights,
+                                  T eps, bool order3);
+template <>
+__device__ __forceinline__ double weno<double>(double a, double b, double c,
+                                               double d, double e, int w,
+                                               double eps, bool o3) {
+  return weno_f64(a, b, c, d, e, w, eps, o3);
+}
+template <>
+__device__ __forceinline__ float weno<float>(float a, float b, float c,
+                                             float d, float e, int w,
+                                             float eps, bool o3) {
+  return weno_f32(a, b, c, d, e, w, eps, o3);
+}
+
+// ---------------------------------------------------------------------------
+// Face state container (face order: rho, u_n, u_t..., p, Gamma, Pi).
+// ---------------------------------------------------------------------------
+template <int NT>
+struct FState {
+  static constexpr int NC = 5 + NT;
+  double v[NC];
+};
+
+// ---------------------------------------------------------------------------
+// HLLC, eqs. (14)-(18).  Averages of eq. (17) read as the Roe-type
+// (sqrt(rho_l) u_l + sqrt(rho_r) u_r)/(sqrt(rho_l) + sqrt(rho_r)) and the
+// Einfeldt-type c^2 with sqrt(rho_r) c_r^2; sign(0) = 0; when S_k equals S*
+// the star flux of that side is its limit F_k (star velocity u_k).
+// Only the star state selected by sign(S*) is formed (both at S* = 0).
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__device__ __forceinline__ void star_flux(const T* q, T Sk, T Ss, T* F,
+                                          T& us) {
+  constexpr int NC = 5 + NT;
+  const T rho = q[0], un = q[1], p = q[2 + NT], G = q[3 + NT], P = q[4 + NT];
+  T ke = un * un;
+#pragma unroll
+  for (int t = 0; t < NT; t++) ke = ke + q[2 + t] * q[2 + t];
+  const T E = G * p + P + T(0.5) * rho * ke;
+  T Uk[NC], Fk[NC];
+  Uk[0] = rho;
+  Uk[1] = rho * un;
+#pragma unroll
+  for (int t = 0; t < NT; t++) Uk[2 + t] = rho * q[2 + t];
+  Uk[2 + NT] = E;
+  Uk[3 + NT] = G;
+  Uk[4 + NT] = P;
+  Fk[0] = rho * un;
+  Fk[1] = rho * un * un + p;
+#pragma unroll
+  for (int t = 0; t < NT; t++) Fk[2 + t] = rho * un * q[2 + t];
+  Fk[2 + NT] = (E + p) * un;
+  Fk[3 + NT] = G * un;
+  Fk[4 + NT] = P * un;
+  const T den = Sk - Ss;
+  if (den == T(0)) {
+#pragma unroll
+    for (int k = 0; k < NC; k++) F[k] = Fk[k];
+    us = un;
+    return;
+  }
+  const T pk = p + rho * (Sk - un) * (Ss - un);
+  const T sp = Sk * pk;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    const T Dk = (k == 1) ? T(1) : ((k == 2 + NT) ? Ss : T(0));
+    F[k] = (Ss * (Sk * Uk[k] - Fk[k]) + sp * Dk) / den;
+  }
+  us = Ss * (Sk - un) / den;
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void hllc(const T* ql, const T* qr, T* F, T& us) {
+  constexpr int NC = 5 + NT;
+  const T rl = ql[0], ul = ql[1], pl = ql[2 + NT];
+  const T rr = qr[0], ur = qr[1], pr = qr[2 + NT];
+  const T cl2 = sound2<T>(rl, pl, ql[3 + NT], ql[4 + NT]);
+  const T cr2 = sound2<T>(rr, pr, qr[3 + NT], qr[4 + NT]);
+  const T cl = sqrt(cl2), cr = sqrt(cr2);
+  const T sl = sqrt(rl), sr = sqrt(rr);
+  const T ubar = (sl * ul + sr * ur) / (sl + sr);
+  const T cbar2 = (sl * cl2 + sr * cr2) / (sl + sr) +
+                  T(0.5) * sl * sr / ((sl + sr) * (sl + sr)) * (ur - ul) *
+                      (ur - ul);
+  const T cbar = sqrt(cbar2);
+  const T Sl = dmin<T>(dmin<T>(ubar - cbar, ul - cl), T(0));
+  const T Sr = dmax<T>(dmax<T>(ubar + cbar, ur + cr), T(0));
+  const T Ss = (pr - pl + rl * ul * (Sl - ul) - rr * ur * (Sr - ur)) /
+               (rl * (Sl - ul) - rr * (Sr - ur));
+  if (Ss != T(0)) {
+    const bool left = Ss > T(0);
+    T qs[NC];
+#pragma unroll
+    for (int k = 0; k < NC; k++) qs[k] = left ? ql[k] : qr[k];
+    star_flux<T, NT>(qs, left ? Sl : Sr, Ss, F, us);
+  } else {
+    T Fl[NC], Fr[NC], usl, usr;
+    star_flux<T, NT>(ql, Sl, Ss, Fl, usl);
+    star_flux<T, NT>(qr, Sr, Ss, Fr, usr);
+#pragma unroll
+    for (int k = 0; k < NC; k++) F[k] = T(0.5) * Fl[k] + T(0.5) * Fr[k];
+    us = T(0.5) * usl + T(0.5) * usr;
+  }
+}
+
+}  // namespace isw

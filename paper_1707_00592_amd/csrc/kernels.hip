@@ -1,0 +1,333 @@
+// Stage kernels and time-step reduction of the WENO-IS operator for gfx950.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "sweep.hpp"
+
+namespace isw {
+
+// LDS accessor for a stencil: component c at stencil position j (0..5).
+struct LdsStencil {
+  const double* base;  // component 0, position 0
+  int cstride, pstride;
+  __device__ __forceinline__ double operator()(int c, int j) const {
+    return base[c * cstride + j * pstride];
+  }
+};
+
+// Tile geometry of a sweep along axis D.  Cells are addressed as
+// a*sA + l*sL + t*sT with l along D, a across (x for D > 0, the combined
+// (y,z) line index for D = 0) and t the remaining axis.
+template <int NDIM, int D>
+struct Geo {
+  int64_t nL, nA, nT, sL, sA, sT;
+  __device__ __forceinline__ Geo(const int64_t* n) {
+    if (D == 0) {
+      nL = n[0]; sL = 1;
+      nA = n[1] * n[2]; sA = n[0];
+      nT = 1; sT = 0;
+    } else if (D == 1) {
+      nL = n[1]; sL = n[0];
+      nA = n[0]; sA = 1;
+      nT = n[2]; sT = n[0] * n[1];
+    } else {
+      nL = n[2]; sL = n[0] * n[1];
+      nA = n[0]; sA = 1;
+      nT = n[1]; sT = n[0];
+    }
+  }
+};
+
+template <typename T, int NDIM, int D, int TL, int TW, int NTHR, bool MLPW>
+__global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
+  constexpr int NC = 4 + NDIM;
+  constexpr int NP = TL + 6;     // staged positions along D
+  constexpr int NF = TL + 1;     // faces along D per tile row
+  constexpr int NWAVE = NTHR / 64;
+  // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
+  __shared__ double sq[NC * TW * NP];
+  __shared__ double sf[(NC + 1) * TW * NF];
+  __shared__ int s_status;
+  __shared__ int s_skip;
+  // learned weights: network + one inference tile per wave
+  __shared__ char smlp[MLPW ? sizeof(MlpLds) + NWAVE * sizeof(MlpInfTile) : 4];
+  MlpLds* mW = reinterpret_cast<MlpLds*>(smlp);
+  MlpInfTile* mT = reinterpret_cast<MlpInfTile*>(smlp + (MLPW ? sizeof(MlpLds) : 0));
+
+  const Geo<NDIM, D> geo(g.n);
+  const int64_t ntl = (geo.nL + TL - 1) / TL;
+  const int64_t bid = blockIdx.x;
+  const int64_t tl = bid % ntl;
+  const int64_t rest = bid / ntl;
+  const int64_t nta = (geo.nA + TW - 1) / TW;
+  const int64_t ta = rest % nta;
+  const int64_t tt = rest / nta;
+  const int64_t l0 = tl * TL, a0 = ta * TW;
+  const int64_t N = g.n[0] * g.n[1] * g.n[2];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_status = ST_OK;
+    // sticky failure: one read per workgroup so that all lanes agree
+    s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
+  }
+  if (MLPW) mlp_stage_bf16(*mW, g.mlp, tid, NTHR);
+  __syncthreads();
+  if (s_skip) return;
+
+  auto lidx = [](int c, int w, int p) {
+    return D == 0 ? (c * TW + w) * NP + p : (c * NP + p) * TW + w;
+  };
+  auto fidx = [](int k, int w, int j) {
+    return D == 0 ? (k * TW + w) * NF + j : (k * NF + j) * TW + w;
+  };
+
+  // 1. stage primitives (FP64) with ghost cells
+  bool bad = false;
+  for (int e = tid; e < TW * NP; e += NTHR) {
+    const int w = D == 0 ? e / NP : e % TW;
+    const int p = D == 0 ? e % NP : e / TW;
+    const int64_t a = a0 + w;
+    const int64_t l = l0 + p - 3;
+    if (a >= geo.nA || l >= geo.nL + 3) continue;
+    bool flip;
+    const int64_t li = bc_index(l, geo.nL, g.bc_lo, g.bc_hi, flip);
+    const int64_t cell = a * geo.sA + li * geo.sL + tt * geo.sT;
+    double q[NC];
+    cell_prim<NDIM>(g.Uin, N, cell, q);
+    if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
+    if (flip) q[1 + D] = -q[1 + D];
+#pragma unroll
+    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = q[c];
+  }
+  if (bad) s_status = ST_NONPHYSICAL;
+  __syncthreads();
+
+  // 2. faces.  The loop trip count is the same for every lane so that the
+  // learned-weights variant can run wave-wide matrix instructions; lanes
+  // without a face of their own evaluate face (0, 0) and store nothing.
+  int my3 = 0, my1 = 0;
+  MlpRun mr;
+  if (MLPW) {
+    mr.W = mW;
+    mr.T = mT + (tid >> 6);
+    mr.thr = g.mlp_thr;
+    mr.fallbacks = 0;
+  }
+  for (int f0 = 0; f0 < TW * NF; f0 += NTHR) {
+    const int f = f0 + tid;
+    int w = D == 0 ? f / NF : f % TW;
+    int j = D == 0 ? f % NF : f / TW;
+    bool valid = f < TW * NF && a0 + w < geo.nA && l0 + j <= geo.nL;
+    if (!MLPW && !valid) continue;
+    if (!valid) {
+      w = 0;
+      j = 0;
+    }
+    LdsStencil st;
+    st.base = &sq[lidx(0, w, j)];
+    st.cstride = D == 0 ? TW * NP : NP * TW;
+    st.pstride = D == 0 ? 1 : TW;
+    double F[NC], us;
+    int n3, n1;
+    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, MLPW ? &mr : nullptr);
+    if (!valid) continue;
+    // the face on a tile boundary is evaluated by both tiles; count it once
+    // (in the tile to its right, or the last tile for the domain's last face)
+    if (j < TL || l0 + j == geo.nL) {
+      my3 += n3;
+      my1 += n1;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
+    sf[fidx(NC, w, j)] = us;
+  }
+  if (g.stats) {
+    if (my3) atomicAdd(&g.stats->o3[D], (unsigned long long)my3);
+    if (my1) atomicAdd(&g.stats->o1[D], (unsigned long long)my1);
+    if (MLPW && mr.fallbacks)
+      atomicAdd(&g.stats->mlp_fallback[D], (unsigned long long)mr.fallbacks);
+  }
+  __syncthreads();
+  if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
+
+  // 3. cells
+  const double dx = g.dx[D];
+  const int mode = g.mode;
+  const bool readR = g.readR != 0;
+  for (int e = tid; e < TW * TL; e += NTHR) {
+    const int w = D == 0 ? e / TL : e % TW;
+    const int j = D == 0 ? e % TL : e / TW;
+    const int64_t a = a0 + w;
+    const int64_t l = l0 + j;
+    if (a >= geo.nA || l >= geo.nL) continue;
+    const int64_t cell = a * geo.sA + l * geo.sL + tt * geo.sT;
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+      const int kc = axis_comp<NDIM, D>(k);
+      double r = -(sf[fidx(k, w, j + 1)] - sf[fidx(k, w, j)]) / dx;
+      if (k >= 3 + (NDIM - 1)) {
+        const double phi = sq[lidx(kc, w, j + 3)];
+        r = r + phi * (sf[fidx(NC, w, j + 1)] - sf[fidx(NC, w, j)]) / dx;
+      }
+      const int64_t o = kc * N + cell;
+      const double L = readR ? g.R[o] + r : r;
+      if (mode == OUT_PARTIAL || mode == OUT_RHS) {
+        g.Rout[o] = L;
+      } else {
+        const double h = *g.dt;
+        if (mode == OUT_RK1) {
+          g.Uout[o] = g.U0[o] + h * L;
+        } else if (mode == OUT_RK2) {
+          g.Uout[o] = 0.75 * g.U0[o] + 0.25 * (g.Uin[o] + h * L);
+        } else {
+          g.Uout[o] = (1.0 / 3.0) * g.U0[o] + (2.0 / 3.0) * (g.Uin[o] + h * L);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Time step: per-cell sum_d (|u_d| + c)/dx_d, a max per workgroup written to
+// partial[], then one workgroup takes the max of the partials and writes
+// dt = cfl / max (clipped to dt_max).  No atomics; the max does not depend on
+// the order, so dt is reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (b > a || b != b) ? b : a;
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void cfl_reduce_kernel(
+    const double* U, int64_t n0, int64_t n1, int64_t n2, double dx0,
+    double dx1, double dx2, double* partial) {
+  const int64_t N = n0 * n1 * n2;
+  const double dxs[3] = {dx0, dx1, dx2};
+  double m = 0.0;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    double q[4 + NDIM];
+    cell_prim<NDIM>(U, N, c, q);
+    const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
+    double s = (fabs(q[1]) + cs) / dxs[0];
+#pragma unroll
+    for (int a = 1; a < NDIM; a++) s = s + (fabs(q[1 + a]) + cs) / dxs[a];
+    m = nanmax(m, s);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial, int nblk,
+                                                           double cfl, double dt_max,
+                                                           double* dt) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = nanmax(m, partial[b]);
+  __shared__ double red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double h = cfl / red[0];
+    if (dt_max > 0.0 && h > dt_max) h = dt_max;
+    *dt = h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int NDIM, int D>
+struct TileShape;
+// x sweeps: 63 cells x 4 rows -> 64 faces per row, one per lane
+template <int NDIM>
+struct TileShape<NDIM, 0> {
+  static constexpr int TL = NDIM == 1 ? 255 : 63;
+  static constexpr int TW = NDIM == 1 ? 1 : 4;
+};
+// y / z sweeps: 16 x-consecutive columns x 15 cells -> 256 faces
+template <int NDIM>
+struct TileShape<NDIM, 1> {
+  static constexpr int TL = 15, TW = 16;
+};
+template <int NDIM>
+struct TileShape<NDIM, 2> {
+  static constexpr int TL = 15, TW = 16;
+};
+
+template <typename T, int NDIM, int D, bool MLPW>
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s) {
+  using TS = TileShape<NDIM, D>;
+  constexpr int NTHR = 256;
+  const int64_t nL = a.n[D];
+  int64_t nA, nT;
+  if (D == 0) { nA = a.n[1] * a.n[2]; nT = 1; }
+  else if (D == 1) { nA = a.n[0]; nT = a.n[2]; }
+  else { nA = a.n[0]; nT = a.n[1]; }
+  const int64_t blocks = ((nL + TS::TL - 1) / TS::TL) * ((nA + TS::TW - 1) / TS::TW) * nT;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MLPW>),
+                     dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool MLPW>
+static hipError_t launch_sweep_p(int ndim, int D, const SweepArgs& a, hipStream_t s) {
+  if (ndim == 1) return launch_sweep_t<T, 1, 0, MLPW>(a, s);
+  if (ndim == 2) {
+    return D == 0 ? launch_sweep_t<T, 2, 0, MLPW>(a, s) : launch_sweep_t<T, 2, 1, MLPW>(a, s);
+  }
+  if (D == 0) return launch_sweep_t<T, 3, 0, MLPW>(a, s);
+  if (D == 1) return launch_sweep_t<T, 3, 1, MLPW>(a, s);
+  return launch_sweep_t<T, 3, 2, MLPW>(a, s);
+}
+
+hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a0, int mode,
+                        bool readR, hipStream_t s) {
+  SweepArgs a = a0;
+  a.mode = mode;
+  a.readR = readR ? 1 : 0;
+  if (a.weights == W_MLP) {
+    if (precision != 1 || !a.mlp) return hipErrorInvalidValue;
+    return launch_sweep_p<float, true>(ndim, D, a, s);
+  }
+  return precision == 1 ? launch_sweep_p<float, false>(ndim, D, a, s)
+                        : launch_sweep_p<double, false>(ndim, D, a, s);
+}
+
+hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
+                      double cfl, double dt_max, double* partial, int max_partial,
+                      double* dt, int ncu, hipStream_t s) {
+  const int64_t N = n[0] * n[1] * n[2];
+  int64_t blocks = (N + 255) / 256;
+  int64_t cap = (int64_t)ncu * 4;
+  if (cap > max_partial) cap = max_partial;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  if (ndim == 1)
+    hipLaunchKernelGGL(cfl_reduce_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
+                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+  else if (ndim == 2)
+    hipLaunchKernelGGL(cfl_reduce_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
+                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+  else
+    hipLaunchKernelGGL(cfl_reduce_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
+                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(256), 0, s, partial, (int)blocks, cfl,
+                     dt_max, dt);
+  return hipGetLastError();
+}
+
+}  // namespace isw

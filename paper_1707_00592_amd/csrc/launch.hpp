@@ -1,0 +1,23 @@
+// Host-side launch entry points of the device kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace isw {
+
+struct SweepArgs;
+struct BatchArgs;
+
+// One axis D of a stage: mode is an OutMode, readR adds the partial sum of
+// the previous axes.  precision: 0 = FP64, 1 = FP32 reconstruction/flux.
+hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
+                        bool readR, hipStream_t s);
+
+// dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); partial is
+// device scratch of max_partial doubles.
+hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
+                      double cfl, double dt_max, double* partial, int max_partial,
+                      double* dt, int ncu, hipStream_t s);
+
+}  // namespace isw

@@ -1,0 +1,319 @@
+// Direction-sweep stage kernel of the WENO-IS finite-volume operator.
+//
+// One launch handles one axis D of an RK stage (Sec. 3, dimension by
+// dimension).  A workgroup owns a tile of TL cells along D by TW cells
+// across it:
+//   1. load U for the tile plus 3 ghost cells per side along D (boundary
+//      conditions applied while loading), recover the primitive state in
+//      FP64 (eq. (2)) and stage it in LDS, latching non-physical cells;
+//   2. one lane per face: project the six stencil cells onto the
+//      characteristic fields (eqs. (11)-(12)), reconstruct both face states
+//      with WENO-IS (eqs. (19)-(28)), back-project (eq. (13)), apply the
+//      MOOD cascade (Sec. 3.4) and evaluate HLLC (eqs. (14)-(18)); the
+//      flux and u^HLLC go to LDS;
+//   3. one lane per cell: the D-contribution to dU/dt, eqs. (5)-(6), added to
+//      the partial sum of the previous axes, and either stored as a partial
+//      sum, stored as dU/dt, or combined into the Runge-Kutta stage.
+// Coalescing: along x the tile rows are contiguous; for y and z sweeps the
+// tile is TW consecutive x cells wide.
+#pragma once
+
+#include "face.hpp"
+#include "mlp.hpp"
+
+namespace isw {
+
+enum OutMode {
+  OUT_PARTIAL = 0,  // R = (R +) r_D
+  OUT_RHS = 1,      // dUdt = (R +) r_D
+  OUT_RK1 = 2,      // Uout = U0 + dt L
+  OUT_RK2 = 3,      // Uout = 3/4 U0 + 1/4 (Uin + dt L)
+  OUT_RK3 = 4       // Uout = 1/3 U0 + 2/3 (Uin + dt L)
+};
+
+enum { ST_OK = 0, ST_NONPHYSICAL = -4 };
+
+struct StatsDev {  // layout of isweno_stats
+  unsigned long long o3[3], o1[3], mlp_fallback[3];
+  int status;
+  int reserved;
+};
+
+struct SweepArgs {
+  const double* Uin;   // stage input (stencil source), nc x N
+  const double* R;     // partial sum of previous axes (when read)
+  double* Rout;        // partial-sum / dUdt output
+  const double* U0;    // U^n for the RK combine
+  double* Uout;        // RK stage output
+  const double* dt;    // device scalar
+  StatsDev* stats;     // may be null
+  int64_t n[3];
+  double dx[3];
+  int bc_lo, bc_hi;    // of axis D
+  int weights, mood;
+  double eps;
+  int mode;            // OutMode of this launch
+  int readR;           // add the partial sum R of the previous axes
+  const uint16_t* mlp; // packed bf16 network (learned weights only)
+  float mlp_thr;
+};
+
+// Boundary map of a ghost/interior position l (-3..n+2) on a line of n
+// cells: interior index and whether the normal velocity is mirrored.
+__device__ __forceinline__ int64_t bc_index(int64_t l, int64_t n, int bclo,
+                                            int bchi, bool& flip) {
+  flip = false;
+  if (l < 0) {
+    if (bclo == 1) return ((l % n) + n) % n;
+    if (bclo == 2) {
+      flip = true;
+      return -l - 1;
+    }
+    return 0;
+  }
+  if (l >= n) {
+    if (bchi == 1) return l % n;
+    if (bchi == 2) {
+      flip = true;
+      return 2 * n - 1 - l;
+    }
+    return n - 1;
+  }
+  return l;
+}
+
+// Primitive recovery of one cell, axis order (rho, u_x.., p, Gamma, Pi),
+// eq. (2): p = (E - rho |u|^2 / 2 - Pi) / Gamma.
+template <int NDIM>
+__device__ __forceinline__ void cell_prim(const double* U, int64_t N,
+                                          int64_t cell, double* q) {
+  const double rho = U[cell];
+  double vel[NDIM];
+#pragma unroll
+  for (int a = 0; a < NDIM; a++) vel[a] = U[(1 + a) * N + cell] / rho;
+  double ke = vel[0] * vel[0];
+#pragma unroll
+  for (int a = 1; a < NDIM; a++) ke = ke + vel[a] * vel[a];
+  const double E = U[(1 + NDIM) * N + cell];
+  const double G = U[(2 + NDIM) * N + cell];
+  const double P = U[(3 + NDIM) * N + cell];
+  q[0] = rho;
+#pragma unroll
+  for (int a = 0; a < NDIM; a++) q[1 + a] = vel[a];
+  q[1 + NDIM] = (E - 0.5 * rho * ke - P) / G;
+  q[2 + NDIM] = G;
+  q[3 + NDIM] = P;
+}
+
+template <int NDIM>
+__device__ __forceinline__ bool cell_ok(const double* U, int64_t N,
+                                        int64_t cell, const double* q) {
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 4 + NDIM; k++) fin = fin && isfinite(U[k * N + cell]);
+  return fin && admissible(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]);
+}
+
+// Face-order component k -> axis-order (LDS / conservative) component.
+template <int NDIM, int D>
+__device__ __host__ constexpr int axis_comp(int k) {
+  return k == 0 ? 0
+         : k == 1 ? 1 + D
+         : (k < 1 + NDIM) ? 1 + ((k - 2) < D ? (k - 2) : (k - 1))
+                          : k;
+}
+
+// Reconstruct the face states at the given order and back-project them to
+// face-order primitives in FP64.  One characteristic field per iteration
+// (the loop is kept rolled to bound register use; the branches on the field
+// index are wave-uniform): project the six stencil cells with the field's
+// row of L (eq. (11)), reconstruct the left state from positions 0..4
+// (i-2..i+2) and the right state from the mirror image 5..1, and add the
+// field's column of R (eq. (13)) into the face states in field order.
+// sides: bit 0 = left, bit 1 = right.  S(c, j) reads LDS component c (axis
+// order) at stencil position j.
+// Learned weights for one field: both sides' weights from the network
+// (two 32-row passes of the wave's tile), the candidates of eq. (20) and
+// eq. (19); below the confidence threshold the eq. (28) weights are used.
+template <typename T>
+__device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, T& rr) {
+  const int l = threadIdx.x & 63;
+  float x[8], z[9];
+  mlp_features<T>(w, mr.f6, mr.f7, x);
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    if ((l >> 5) == h) {
+#pragma unroll
+      for (int k = 0; k < 8; k++) mr.T->x[(l & 31) * 8 + k] = f2bf(x[k]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    mlp_forward32(*mr.W, mr.T->x, mr.T->h1, mr.T->h2, mr.T->z);
+    if ((l >> 5) == h) {
+#pragma unroll
+      for (int k = 0; k < 9; k++) z[k] = mr.T->z[(l & 31) * 16 + k];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  const float conf = 1.0f / (1.0f + __expf(-z[8]));
+  if (!(conf >= mr.thr)) {
+    rl = weno<T>(w[0], w[1], w[2], w[3], w[4], W_MODIFIED, eps, false);
+    rr = weno<T>(w[5], w[4], w[3], w[2], w[1], W_MODIFIED, eps, false);
+    mr.fallbacks++;
+    return;
+  }
+#pragma unroll
+  for (int side = 0; side < 2; side++) {
+    const float* zs = z + 4 * side;
+    const float m = fmaxf(fmaxf(zs[0], zs[1]), fmaxf(zs[2], zs[3]));
+    float e[4], sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      e[k] = __expf(zs[k] - m);
+      sum += e[k];
+    }
+    const T A = side ? w[5] : w[0], B = side ? w[4] : w[1], C = side ? w[3] : w[2],
+            D_ = side ? w[2] : w[3], E = side ? w[1] : w[4];
+    const T c1 = (C + D_) / T(2), c2 = (T(3) * C - B) / T(2);
+    const T c3 = (T(2) * C + T(5) * D_ - E) / T(6), c4 = (T(2) * A - T(7) * B + T(11) * C) / T(6);
+    const T q = (T(e[0]) * c1 + T(e[1]) * c2 + T(e[2]) * c3 + T(e[3]) * c4) / T(sum);
+    if (side) rr = q; else rl = q;
+  }
+}
+
+template <typename T, int NDIM, int D, class S>
+__device__ __forceinline__ void recon(const S& st, int sides, bool order3, int weights, T eps,
+                                      T a, T b, double bd, double gd, double* ql, double* qr,
+                                      MlpRun* mr = nullptr) {
+  constexpr int NT = NDIM - 1, NC = 5 + NT;
+  constexpr int CR = 0, CU = 1 + D, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
+#pragma unroll 1
+  for (int m = 0; m < NC; m++) {
+    // row of L: 0 = acoustic (sign sa), 1 = entropy, 2 = copy of component cx
+    int kind = 2, cx = CG;
+    T sa = a;
+    if (m == 0) {
+      kind = 0;
+      sa = -a;
+    } else if (m == NC - 1) {
+      kind = 0;
+    } else if (m == 1) {
+      kind = 1;
+    } else if (m < 2 + NT) {
+      cx = 1 + ((m - 2) < D ? (m - 2) : (m - 1));
+    } else if (m == 3 + NT) {
+      cx = CPI;
+    }
+    T w[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+      if (kind == 0) {
+        w[j] = sa * T(st(CU, j)) + T(0.5) * T(st(CP, j));
+      } else if (kind == 1) {
+        w[j] = T(st(CR, j)) - b * T(st(CP, j));
+      } else {
+        w[j] = T(st(cx, j));
+      }
+    }
+    T rlm = T(0), rrm = T(0);
+    const bool learned = mr != nullptr && !order3;
+    if (learned) mlp_field<T>(w, *mr, eps, rlm, rrm);
+    const int wk = weights == W_MLP ? W_MODIFIED : weights;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      if (!(sides & (1 << side))) continue;
+      double* q = side ? qr : ql;
+      const double r =
+          learned ? double(side ? rrm : rlm)
+          : side ? double(weno<T>(w[5], w[4], w[3], w[2], w[1], wk, eps, order3))
+                 : double(weno<T>(w[0], w[1], w[2], w[3], w[4], wk, eps, order3));
+      if (m == 0) {
+        q[0] = bd * r;
+        q[1] = (-gd) * r;
+        q[2 + NT] = r;
+      } else if (m == 1) {
+        q[0] = q[0] + r;
+      } else if (m == NC - 1) {
+        q[0] = q[0] + bd * r;
+        q[1] = q[1] + gd * r;
+        q[2 + NT] = q[2 + NT] + r;
+      } else {
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+          if (m == 2 + t) q[2 + t] = r;
+        if (m == 2 + NT) q[3 + NT] = r;
+        if (m == 3 + NT) q[4 + NT] = r;
+      }
+    }
+  }
+}
+
+// Full face: average state, eigen-parameters, both reconstructions, MOOD
+// cascade, HLLC.  F (face order) and us are written; o3/o1 report the
+// orders used (per side).
+template <typename T, int NDIM, int D, class S>
+__device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
+                                          double eps, double* F, double& us,
+                                          int& n3, int& n1, MlpRun* mr = nullptr) {
+  constexpr int NT = NDIM - 1, NC = 5 + NT;
+  constexpr int CR = 0, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
+  // L_{i+1/2}: L of eq. (11) at the mean of the two primitive states.
+  const double rb = 0.5 * (st(CR, 2) + st(CR, 3));
+  const double pb = 0.5 * (st(CP, 2) + st(CP, 3));
+  const double Gb = 0.5 * (st(CG, 2) + st(CG, 3));
+  const double Pb = 0.5 * (st(CPI, 2) + st(CPI, 3));
+  T a, b;
+  double bd, gd;
+  {
+    const T c2 = sound2<T>(T(rb), T(pb), T(Gb), T(Pb));
+    const T c = sqrt(c2);
+    a = T(rb) * c / T(2);
+    b = T(1) / c2;
+    bd = double(b);
+    gd = 1.0 / double(T(rb) * c);
+    if (sizeof(T) == 8) {
+      bd = 1.0 / double(c2);
+    }
+  }
+  double ql[NC], qr[NC];
+  if (mr) mlp_material(Gb, Pb, mr->f6, mr->f7);
+  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, mr);
+  n3 = 0;
+  n1 = 0;
+  if (mood) {
+    // Sec. 3.4: redo a failing side without the 3-point stencils, then fall
+    // back to the first-order state of eq. (32) (the cell's own primitive
+    // state, since R L q_i = q_i).
+    const int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
+                     (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
+    if (fail) {
+      recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr);
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        if (!(fail & (1 << side))) continue;
+        double* q = side ? qr : ql;
+        if (admissible(q[0], q[2 + NT], q[3 + NT], q[4 + NT])) {
+          n3++;
+        } else {
+          const int j = side ? 3 : 2;
+#pragma unroll
+          for (int k = 0; k < NC; k++) q[k] = st(axis_comp<NDIM, D>(k), j);
+          n1++;
+        }
+      }
+    }
+  }
+  T tl[NC], tr[NC], tF[NC], tus;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    tl[k] = T(ql[k]);
+    tr[k] = T(qr[k]);
+  }
+  hllc<T, NT>(tl, tr, tF, tus);
+#pragma unroll
+  for (int k = 0; k < NC; k++) F[k] = double(tF[k]);
+  us = double(tus);
+}
+
+}  // namespace isw

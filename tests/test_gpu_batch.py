@@ -1,0 +1,135 @@
+"""GPU parity of the batched 1D form (isweno_batch_*) against the oracle.
+
+FP64: bit-for-bit with the oracle's batch driver (same per-face operation
+order), for every tile configuration the autotuner can pick, for graph
+replays of several steps and at the full 4096-problem size on sampled
+problems.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_00592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _small_batch():
+    return wl.batch_riemann(37, seed=5, nmin=3, nmax=700)
+
+
+def test_batch_step_matches_oracle(lib, ctx):
+    import torch
+    b = _small_batch()
+    o = oracle.make_opts(mood=True, cfl=0.5)
+    ref, dtr, st, s = oracle.batch_step(b["U"], b["offsets"], b["dx"], o, nsteps=3)
+    assert s == 0
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    U = _dev(b["U"])
+    dt = torch.zeros(len(b["dx"]), dtype=torch.float64, device="cuda")
+    stats = lib.new_stats()
+    plan.step(U, lib.make_opts(mood=True, cfl=0.5), dt, nsteps=3, stats=stats)
+    got = U.cpu().numpy()
+    print("[batch] bitwise:", np.array_equal(got, ref), flush=True)
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_array_equal(dt.cpu().numpy(), dtr)
+    s2 = lib.read_stats(stats)
+    assert s2.status == 0 and (s2.o3[0], s2.o1[0]) == (st.o3[0], st.o1[0])
+
+
+def test_every_tile_configuration_gives_identical_results(lib, ctx):
+    """Tile-shape invariance: the autotuner's candidates (tile length 63,
+    127, 255 and 2..16 blocks per CU) all produce the same bits."""
+    import torch
+    b = _small_batch()
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    opts = lib.make_opts(mood=True, cfl=0.5)
+    outs = []
+    U0 = _dev(b["U"])
+    for _ in range(2):
+        chosen = plan.autotune(U0, opts)
+        assert chosen in (63, 127, 255)
+        U = U0.clone()
+        dt = torch.zeros(len(b["dx"]), dtype=torch.float64, device="cuda")
+        plan.step(U, opts, dt, nsteps=2)
+        outs.append(U.cpu().numpy())
+    ref, *_ = oracle.batch_step(b["U"], b["offsets"], b["dx"], oracle.make_opts(), nsteps=2)
+    for o in outs:
+        np.testing.assert_array_equal(o, ref)
+
+
+def test_batch_equals_single_problem_calls(lib, ctx):
+    import torch
+    b = wl.batch_riemann(5, seed=8, nmin=100, nmax=300)
+    opts = lib.make_opts(mood=True, cfl=0.5)
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    U = _dev(b["U"])
+    dt = torch.zeros(5, dtype=torch.float64, device="cuda")
+    plan.step(U, opts, dt, nsteps=2)
+    got = U.cpu().numpy()
+    for k in range(5):
+        sl = slice(b["offsets"][k], b["offsets"][k + 1])
+        Uk = _dev(b["U"][:, sl])
+        g = lib.make_grid((sl.stop - sl.start,), (b["dx"][k],))
+        d1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(2):
+            ctx.rk3_step(Uk, g, opts, d1)
+        np.testing.assert_array_equal(got[:, sl], Uk.cpu().numpy())
+
+
+def test_fixed_dt_and_reflective_ends(lib, ctx):
+    import torch
+    b = wl.batch_riemann(9, seed=3, nmin=3, nmax=200)
+    dt0 = 0.1 * b["dx"] / 2000.0
+    o = oracle.make_opts(mood=True, cfl=0.0)
+    ref, *_ = oracle.batch_step(b["U"], b["offsets"], b["dx"], o, dt=dt0, nsteps=2,
+                                bc_lo=2, bc_hi=1)
+    plan = ctx.batch_plan(b["offsets"], b["dx"], bc_lo=2, bc_hi=1)
+    U = _dev(b["U"])
+    plan.step(U, lib.make_opts(cfl=0.0), _dev(dt0), nsteps=2)
+    np.testing.assert_array_equal(U.cpu().numpy(), ref)
+
+
+def test_full_size_batch_sampled(lib, ctx):
+    """The 4096-problem workload (lengths 128..4096) in the launch
+    configuration the autotuner picks: one step, 40 problems checked
+    against the oracle."""
+    import torch
+    b = wl.batch_riemann(4096, seed=1707)
+    opts = lib.make_opts(mood=True, cfl=0.5)
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    U = _dev(b["U"])
+    plan.autotune(U, opts)
+    dt = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    stats = lib.new_stats()
+    plan.step(U, opts, dt, nsteps=1, stats=stats)
+    got = U.cpu().numpy()
+    assert lib.read_stats(stats).status == 0
+    rs = np.random.default_rng(0)
+    pick = rs.choice(4096, size=40, replace=False)
+    off = b["offsets"]
+    sizes = [off[k + 1] - off[k] for k in pick]
+    sub_off = np.concatenate([[0], np.cumsum(sizes)])
+    sub_U = np.concatenate([b["U"][:, off[k]:off[k + 1]] for k in pick], axis=1)
+    ref, *_ = oracle.batch_step(sub_U, sub_off, b["dx"][pick], oracle.make_opts(), nsteps=1)
+    for i, k in enumerate(pick):
+        np.testing.assert_array_equal(got[:, off[k]:off[k + 1]], ref[:, sub_off[i]:sub_off[i + 1]])
+
+
+def test_plan_argument_errors(lib, ctx):
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.batch_plan(np.array([0, 5, 5]), np.array([0.1, 0.1]))      # empty problem
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.batch_plan(np.array([0, 2, 9]), np.array([0.1, 0.1]), bc_lo=2)  # reflective, n < 3
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.batch_plan(np.array([0, 5]), np.array([-1.0]))

@@ -1,0 +1,199 @@
+"""The learned-weights form: bf16 matrix-core training and inference kernels
+against the FP64 reference network of the oracle, and what the trained
+network does in the solver.
+
+Bounds (bf16 weights and activations carry 8 significant bits):
+  * forward logits within 3e-2 * (1 + |z|) of the FP64 network evaluated on
+    the same bf16-rounded parameters and inputs;
+  * loss within 2 % and the gradient within 5 % (relative 2-norm, cosine
+    similarity > 0.998) of the FP64 gradient;
+  * Adam and bf16 packing match their definitions to float32 rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_00592_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _bf16(a):
+    """Round float32 to bf16 (nearest even) and back, on the host."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _params(seed=0, scale=0.4):
+    rs = np.random.default_rng(seed)
+    return (rs.normal(scale=scale, size=oracle.MLP_NPARAM)).astype(np.float32)
+
+
+def test_forward_matches_reference(lib, ctx):
+    import torch
+    rs = np.random.default_rng(1)
+    P = _params(1)
+    n = 1000  # several 32-row tiles and a ragged tail
+    X = rs.uniform(0, 1, size=(n, 8)).astype(np.float32)
+    out = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(_dev(P), _dev(X), out)
+    got = out.cpu().numpy()
+    ref = oracle.mlp_forward(_bf16(P).astype(np.float64), _bf16(X).astype(np.float64))
+    err = np.abs(got - ref) / (1.0 + np.abs(ref))
+    print(f"[mlp] forward max scaled err {err.max():.3e}", flush=True)
+    assert err.max() < 3e-2
+
+
+def test_loss_and_gradient_match_reference(lib, ctx):
+    import torch
+    rs = np.random.default_rng(2)
+    P = _params(2, 0.3)
+    n = 777
+    X = rs.uniform(0, 1, size=(n, 8)).astype(np.float32)
+    Y = rs.dirichlet(np.ones(4), size=(n, 2)).reshape(n, 8).astype(np.float32)
+    Cc = (rs.random(n) < 0.5).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros(oracle.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), _dev(Cc), loss, grad)
+    g = grad.cpu().numpy().astype(np.float64)
+    lref, gref = oracle.mlp_loss_grad(_bf16(P).astype(np.float64), _bf16(X).astype(np.float64),
+                                      Y.astype(np.float64), Cc.astype(np.float64))
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    cos = g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref))
+    print(f"[mlp] loss {float(loss.item()):.6f} ref {lref:.6f}; grad rel {rel:.3e} cos {cos:.6f}",
+          flush=True)
+    assert abs(float(loss.item()) - lref) <= 0.02 * abs(lref)
+    assert rel < 0.05 and cos > 0.998
+    # deterministic: a second evaluation gives the same bits
+    grad2 = torch.zeros_like(grad)
+    ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), _dev(Cc), loss, grad2)
+    assert torch.equal(grad, grad2)
+
+
+def test_kernel_formed_confidence_targets(lib, ctx):
+    """C = NULL: the target is 1 where both predicted heads are within 0.05
+    (L1) of the target weights; equals passing those labels explicitly."""
+    import torch
+    rs = np.random.default_rng(3)
+    P = _params(3, 0.3)
+    n = 300
+    X = rs.uniform(0, 1, size=(n, 8)).astype(np.float32)
+    out = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(_dev(P), _dev(X), out)
+    z = out.cpu().numpy().astype(np.float64)
+    soft = lambda a: np.exp(a - a.max(1, keepdims=True)) / np.exp(a - a.max(1, keepdims=True)).sum(1, keepdims=True)
+    Yh = np.concatenate([soft(z[:, :4]), soft(z[:, 4:8])], axis=1)
+    Y = Yh + rs.choice([0.0, 0.1], size=(n, 1)) * np.array([1, -1, 0, 0, 0, 0, 0, 0])
+    Y = Y.astype(np.float32)
+    dist = np.maximum(np.abs(Yh[:, :4] - Y[:, :4]).sum(1), np.abs(Yh[:, 4:] - Y[:, 4:]).sum(1))
+    C = (dist < 0.05).astype(np.float32)
+    assert 0 < C.sum() < n
+    l1 = torch.zeros(1, device="cuda"); l2 = torch.zeros(1, device="cuda")
+    g1 = torch.zeros(oracle.MLP_NPARAM, device="cuda"); g2 = torch.zeros_like(g1)
+    ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), None, l1, g1)
+    ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), _dev(C), l2, g2)
+    assert float(l1.item()) == pytest.approx(float(l2.item()), rel=1e-5)
+    np.testing.assert_allclose(g1.cpu().numpy(), g2.cpu().numpy(), rtol=1e-4, atol=1e-7)
+
+
+def test_adam_step(lib, ctx):
+    import torch
+    rs = np.random.default_rng(4)
+    P = rs.normal(size=oracle.MLP_NPARAM).astype(np.float32)
+    G = rs.normal(size=oracle.MLP_NPARAM).astype(np.float32)
+    M = rs.normal(size=oracle.MLP_NPARAM).astype(np.float32) * 0.1
+    V = rs.uniform(0, 1, size=oracle.MLP_NPARAM).astype(np.float32) * 0.1
+    p, m, v = _dev(P), _dev(M), _dev(V)
+    ctx.mlp_adam(p, _dev(G), m, v, 3, 1e-3, 0.9, 0.999, 1e-8)
+    b1, b2, lr, eps, t = 0.9, 0.999, 1e-3, 1e-8, 3
+    m_ref = b1 * M + (1 - b1) * G
+    v_ref = b2 * V + (1 - b2) * G * G
+    p_ref = P - lr * (m_ref / (1 - b1 ** t)) / (np.sqrt(v_ref / (1 - b2 ** t)) + eps)
+    np.testing.assert_allclose(m.cpu().numpy(), m_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(v.cpu().numpy(), v_ref, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(p.cpu().numpy(), p_ref, rtol=1e-6, atol=1e-6)
+
+
+def test_pack_rounds_to_nearest_even(lib, ctx):
+    import torch
+    P = _params(5)
+    packed = torch.zeros(oracle.MLP_NPARAM, dtype=torch.int16, device="cuda")
+    ctx.mlp_pack(_dev(P), packed)
+    got = (packed.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    np.testing.assert_array_equal(got, _bf16(P))
+
+
+def test_samples_match_reference_weights(lib, ctx):
+    """Inputs and targets of isweno_mlp_samples against the oracle's own
+    projection (L of eq. (11)) and weights (eq. (28)) on the same faces."""
+    import torch
+    p = wl.random_two_phase((40,), seed=6)
+    ig = lib.make_grid(p.n, p.dx, 0, 0)
+    n_rows = 41 * 5
+    X = torch.zeros((n_rows, 8), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((n_rows, 8), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.mlp_samples(_dev(p.U), ig, lib.make_opts(), X, Y, n_rows, 1, cnt)
+    assert int(cnt.item()) == n_rows
+    Xh, Yh = X.cpu().numpy(), Y.cpu().numpy()
+    pr = wl.cons_to_prim(p.U, 1)
+    q = np.stack([p.U[0], pr["vel"][0], pr["p"], p.U[3], p.U[4]], axis=1)
+    ext = np.concatenate([np.repeat(q[:1], 3, 0), q, np.repeat(q[-1:], 3, 0)])
+    for f in range(41):
+        q6 = ext[f:f + 6]
+        L, _ = oracle.eigen(0.5 * (q6[2] + q6[3]), 0)
+        w = q6 @ L.T
+        for m in range(5):
+            row = f * 5 + m
+            wl_ = oracle.weno_weights(w[:5, m])
+            wr_ = oracle.weno_weights(w[5:0:-1, m])
+            np.testing.assert_allclose(Yh[row], np.concatenate([wl_, wr_]), rtol=2e-6, atol=2e-7)
+            lo, hi = w[:, m].min(), w[:, m].max()
+            feat = (w[:, m] - lo) / (hi - lo) if hi > lo else np.zeros(6)
+            np.testing.assert_allclose(Xh[row, :6], feat, rtol=1e-5, atol=1e-6)
+
+
+def test_training_and_learned_weights_in_the_solver(lib, ctx):
+    """Train on faces from plain runs (gas-liquid shock tube and a small
+    shock-droplet), then run the shock tube with the learned weights: the
+    loss drops, the run stays physical, and its error against the exact
+    solution is reported next to the plain FP32 path's."""
+    import torch
+    from paper_1707_00592_amd import learned
+    opts64 = lib.make_opts()
+    X, Y = learned.collect(ctx, [wl.sod_gas_liquid(200), wl.shock_droplet_3d(24, 3.0)],
+                           opts64, steps=20, every=5, stride=3, max_rows=200000)
+    Xs, Ys = learned.stratify(X, Y)
+    P, hist = learned.train(ctx, Xs, Ys, steps=400, batch=8192, lr=3e-3, log_every=100)
+    print(f"[mlp] samples {Xs.shape[0]} loss history {hist}", flush=True)
+    assert hist[-1][1] < 0.8 * hist[0][1]
+    ev = learned.evaluate(ctx, P, Xs, Ys)
+    print(f"[mlp] eval {ev}", flush=True)
+    packed = torch.zeros(lib.MLP_NPARAM, dtype=torch.int16, device="cuda")
+    ctx.mlp_pack(P, packed)
+    p = wl.sod_gas_liquid(200)
+    g = lib.make_grid(p.n, p.dx, 0, 0)
+    res = {}
+    for name, o in (("fp32", lib.make_opts(precision=lib.FP32, mood=False)),
+                    ("mlp", lib.make_opts(precision=lib.FP32, weights=lib.W_MLP, mood=False,
+                                          mlp_params=packed))):
+        U = _dev(p.U)
+        st = lib.new_stats()
+        lib.Solver(g, o, ctx).run(U, t_end=p.t_end, stats=st)
+        s = lib.read_stats(st)
+        assert s.status == 0
+        W = oracle.exact_sample(p.extra["WL"], p.extra["WR"], (p.extra["x"] - 0.7) / p.t_end)
+        res[name] = (np.abs(U.cpu().numpy()[0] - W[:, 0]).mean() / 1000.0, s.mlp_fallback[0])
+    print(f"[mlp] shock tube L1(rho)/1000: {res}", flush=True)
+    assert res["mlp"][0] < 2.0 * res["fp32"][0]
