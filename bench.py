@@ -61,7 +61,115 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--extras", default="",
+                    help="other workloads to report: 3d (256^3 shock-droplet), batch "
+                         "(4096 uneven tubes), mlp (learned weights); empty for none")
     return ap.parse_args()
+
+
+def l1_rel(a, b):
+    return float((a - b).abs().sum() / b.abs().sum())
+
+
+def run_steps(isweno, ctx, p, U0, opts, steps, warmup, torch):
+    """Untimed warmup, then `steps` RK3 steps; returns (U, seconds, stats)."""
+    grid = isweno.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    U = U0.clone()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = isweno.new_stats()
+    for _ in range(warmup):
+        ctx.rk3_step(U, grid, opts, dt, st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.rk3_step(U, grid, opts, dt, st)
+    torch.cuda.synchronize()
+    return U, time.perf_counter() - t0, isweno.read_stats(st)
+
+
+def extra_3d(isweno, workloads, ctx, torch, steps=200):
+    """3D shock-droplet 256^3, FP32 reconstruction with FP64 recovery, vs the
+    FP64 path on the same steps; HBM roofline from algorithmic bytes."""
+    p = workloads.shock_droplet_3d(256)
+    U0 = torch.from_numpy(p.U).to("cuda")
+    del p.U
+    out = {"workload": "3D shock-droplet 256^3, MOOD on, CFL 0.5", "steps": steps}
+    res = {}
+    for name, prec in (("fp32", isweno.FP32), ("fp64", isweno.FP64)):
+        U, el, st = run_steps(isweno, ctx, p, U0, isweno.make_opts(precision=prec), steps, 2,
+                              torch)
+        v = p.ncells * 3 * steps / el
+        bw = v * BYTES_PER_CELL_STAGE(3) / 1e9
+        res[name] = U
+        out[name] = {"value": v, "unit": "cell-updates/s per RK stage", "status": st.status,
+                     "hbm_roofline": {"bound": "hbm", "achieved": round(bw, 1),
+                                      "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                                      "frac": round(bw / PEAK["hbm_gbs"], 4),
+                                      "bytes_per_cell_stage": round(BYTES_PER_CELL_STAGE(3), 1)}}
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["fp32"]["l1_rel_rho_vs_fp64"] = l1_rel(res["fp32"][0], res["fp64"][0])
+    del res, U0
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_batch(isweno, workloads, ctx, torch, steps=100):
+    """4096 uneven two-phase shock tubes, one HIP graph per RK3 step,
+    autotuned tiles; FP64 and FP32."""
+    b = workloads.batch_riemann(4096, seed=1707)
+    total = int(b["offsets"][-1])
+    U0 = torch.from_numpy(b["U"]).to("cuda")
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    out = {"workload": f"4096 uneven 1D two-phase shock tubes ({total} cells)", "steps": steps}
+    res = {}
+    for name, prec in (("fp64", isweno.FP64), ("fp32", isweno.FP32)):
+        opts = isweno.make_opts(precision=prec)
+        tile = plan.autotune(U0, opts)
+        U = U0.clone()
+        dt = torch.zeros(4096, dtype=torch.float64, device="cuda")
+        st = isweno.new_stats()
+        plan.step(U, opts, dt, 2, st)            # capture the graph, warm up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(U, opts, dt, steps, st)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = U
+        out[name] = {"value": total * 3 * steps / el, "unit": "cell-updates/s per RK stage",
+                     "tile": tile, "status": isweno.read_stats(st).status}
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["fp32"]["l1_rel_rho_vs_fp64"] = l1_rel(res["fp32"][0], res["fp64"][0])
+    plan.close()
+    return out
+
+
+def extra_mlp(isweno, workloads, ctx, torch, p2, U2, steps, base_U):
+    """Learned weights: trained on the GPU on faces of plain runs of the
+    gas-liquid shock tube and the 3D shock-droplet (at 96^3), then run on
+    the 2D shock-bubble next to the FP32 form."""
+    from paper_1707_00592_amd import learned
+    t0 = time.perf_counter()
+    opts64 = isweno.make_opts()
+    X, Y = learned.collect(ctx, [workloads.sod_gas_liquid(200)], opts64, steps=250, every=10,
+                           stride=1, max_rows=20000)
+    X3, Y3 = learned.collect(ctx, [workloads.shock_droplet_3d(96, radius_cells=12.0)], opts64,
+                             steps=100, every=20, stride=29, max_rows=1_000_000)
+    X = torch.cat([X, X3]); Y = torch.cat([Y, Y3])
+    Xs, Ys = learned.stratify(X, Y, limit=4_000_000)
+    P, hist = learned.train(ctx, Xs, Ys, steps=3000, batch=65536, lr=3e-3, log_every=500)
+    ev = learned.evaluate(ctx, P, Xs, Ys)
+    train_s = time.perf_counter() - t0
+    packed = torch.zeros(isweno.MLP_NPARAM, dtype=torch.int16, device="cuda")
+    ctx.mlp_pack(P, packed)
+    opts = isweno.make_opts(precision=isweno.FP32, weights=isweno.W_MLP, mlp_params=packed,
+                            mlp_conf_threshold=0.5)
+    U, el, st = run_steps(isweno, ctx, p2, U2, opts, steps, 10, torch)
+    faces = sum(p2.ncells // p2.n[d] * (p2.n[d] + 1) for d in range(2)) * 6 * 3 * (steps + 10)
+    return {"value": p2.ncells * 3 * steps / el, "status": st.status,
+            "fallback_rate": float(sum(st.mlp_fallback[:2])) / faces,
+            "l1_rel_rho_vs_fp64": l1_rel(U[0], base_U[0]),
+            "training": {"samples": int(Xs.shape[0]), "adam_steps": 3000, "seconds": train_s,
+                         "loss": hist, **ev}}
 
 
 def run_form(isweno, ctx, p, U0, opts, steps, warmup, torch):
@@ -189,7 +297,21 @@ def main():
                         "l1_rel_E_vs_fp64": rel_l1(r["U"][3], base["U"][3]),
                         "status": r["stats"].status,
                         "roofline": roofline(r["kern"], p, "f32")}
+    extras = [e.strip() for e in args.extras.split(",") if e.strip()]
+    if "mlp" in extras:
+        m = extra_mlp(isweno, workloads, ctx, torch, p, U0, args.steps, base["U"])
+        m["speedup_vs_fp64"] = m["value"] / value
+        if "fp32" in results:
+            m["speedup_vs_fp32"] = m["value"] / forms_out["fp32"]["value"]
+        forms_out["mlp"] = m
     out["forms"] = forms_out
+    other = {}
+    if "3d" in extras:
+        other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)
+    if "batch" in extras:
+        other["batch_riemann"] = extra_batch(isweno, workloads, ctx, torch)
+    if other:
+        out["other_workloads"] = other
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     if args.copy_probe:

@@ -13,8 +13,7 @@ struct isweno_ctx {
   int ncu = 256;
   double* ws = nullptr;          // two state-sized buffers (U1, U2)
   size_t ws_bytes = 0;
-  double* partial = nullptr;     // time-step reduction partials
-  static constexpr int kPartial = 4096;
+  unsigned long long* maxbits = nullptr;  // time-step reduction word
   // kernel timing
   struct Rec {
     int kind;
@@ -185,7 +184,8 @@ int isweno_create(isweno_ctx** out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->ncu = prop.multiProcessorCount;
-  if (hipMalloc(&c->partial, sizeof(double) * isweno_ctx::kPartial) != hipSuccess) {
+  if (hipMalloc(&c->maxbits, 256) != hipSuccess ||
+      hipMemset(c->maxbits, 0, 256) != hipSuccess) {
     delete c;
     return ISWENO_ERR_DEVICE;
   }
@@ -198,7 +198,7 @@ void isweno_destroy(isweno_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->ws) (void)hipFree(c->ws);
-  if (c->partial) (void)hipFree(c->partial);
+  if (c->maxbits) (void)hipFree(c->maxbits);
   drain_timing(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
@@ -230,8 +230,7 @@ int isweno_cfl_dt(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, con
   if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   KTimer t(c, ISWENO_K_CFL, s);
-  return isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->partial,
-                         isweno_ctx::kPartial, dt, c->ncu,
+  return isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt, c->ncu,
                          s) == hipSuccess
              ? ISWENO_OK
              : ISWENO_ERR_DEVICE;
@@ -253,8 +252,7 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (o->cfl > 0.0) {
     KTimer t(c, ISWENO_K_CFL, s);
-    if (isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->partial,
-                         isweno_ctx::kPartial, dt, c->ncu, s) !=
+    if (isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt, c->ncu, s) !=
         hipSuccess)
       return ISWENO_ERR_DEVICE;
   }

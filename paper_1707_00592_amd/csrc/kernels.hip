@@ -38,21 +38,17 @@ struct Geo {
   }
 };
 
-template <typename T, int NDIM, int D, int TL, int TW, int NTHR, bool MLPW>
+template <typename T, int NDIM, int D, int TL, int TW, int NTHR, int MODE,
+          bool READ_R>
 __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   constexpr int NC = 4 + NDIM;
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
-  constexpr int NWAVE = NTHR / 64;
   // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
   __shared__ double sq[NC * TW * NP];
   __shared__ double sf[(NC + 1) * TW * NF];
   __shared__ int s_status;
   __shared__ int s_skip;
-  // learned weights: network + one inference tile per wave
-  __shared__ char smlp[MLPW ? sizeof(MlpLds) + NWAVE * sizeof(MlpInfTile) : 4];
-  MlpLds* mW = reinterpret_cast<MlpLds*>(smlp);
-  MlpInfTile* mT = reinterpret_cast<MlpInfTile*>(smlp + (MLPW ? sizeof(MlpLds) : 0));
 
   const Geo<NDIM, D> geo(g.n);
   const int64_t ntl = (geo.nL + TL - 1) / TL;
@@ -70,7 +66,6 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     // sticky failure: one read per workgroup so that all lanes agree
     s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
   }
-  if (MLPW) mlp_stage_bf16(*mW, g.mlp, tid, NTHR);
   __syncthreads();
   if (s_skip) return;
 
@@ -102,38 +97,24 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
 
-  // 2. faces.  The loop trip count is the same for every lane so that the
-  // learned-weights variant can run wave-wide matrix instructions; lanes
-  // without a face of their own evaluate face (0, 0) and store nothing.
+  // 2. faces
   int my3 = 0, my1 = 0;
-  MlpRun mr;
-  if (MLPW) {
-    mr.W = mW;
-    mr.T = mT + (tid >> 6);
-    mr.thr = g.mlp_thr;
-    mr.fallbacks = 0;
-  }
-  for (int f0 = 0; f0 < TW * NF; f0 += NTHR) {
-    const int f = f0 + tid;
-    int w = D == 0 ? f / NF : f % TW;
-    int j = D == 0 ? f % NF : f / TW;
-    bool valid = f < TW * NF && a0 + w < geo.nA && l0 + j <= geo.nL;
-    if (!MLPW && !valid) continue;
-    if (!valid) {
-      w = 0;
-      j = 0;
-    }
+  for (int f = tid; f < TW * NF; f += NTHR) {
+    const int w = D == 0 ? f / NF : f % TW;
+    const int j = D == 0 ? f % NF : f / TW;
+    const int64_t a = a0 + w;
+    const int64_t gl = l0 + j;  // face index along D (between gl-1 and gl)
+    if (a >= geo.nA || gl > geo.nL) continue;
     LdsStencil st;
     st.base = &sq[lidx(0, w, j)];
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
     double F[NC], us;
     int n3, n1;
-    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, MLPW ? &mr : nullptr);
-    if (!valid) continue;
+    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1);
     // the face on a tile boundary is evaluated by both tiles; count it once
     // (in the tile to its right, or the last tile for the domain's last face)
-    if (j < TL || l0 + j == geo.nL) {
+    if (j < TL || gl == geo.nL) {
       my3 += n3;
       my1 += n1;
     }
@@ -141,19 +122,19 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
     sf[fidx(NC, w, j)] = us;
   }
-  if (g.stats) {
-    if (my3) atomicAdd(&g.stats->o3[D], (unsigned long long)my3);
-    if (my1) atomicAdd(&g.stats->o1[D], (unsigned long long)my1);
-    if (MLPW && mr.fallbacks)
-      atomicAdd(&g.stats->mlp_fallback[D], (unsigned long long)mr.fallbacks);
+  if (g.stats && g.mood) {
+    const unsigned long long b3 = __ballot(my3 != 0);
+    const unsigned long long b1 = __ballot(my1 != 0);
+    if (b3 | b1) {
+      if (my3) atomicAdd(&g.stats->o3[D], (unsigned long long)my3);
+      if (my1) atomicAdd(&g.stats->o1[D], (unsigned long long)my1);
+    }
   }
   __syncthreads();
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
 
   // 3. cells
   const double dx = g.dx[D];
-  const int mode = g.mode;
-  const bool readR = g.readR != 0;
   for (int e = tid; e < TW * TL; e += NTHR) {
     const int w = D == 0 ? e / TL : e % TW;
     const int j = D == 0 ? e % TL : e / TW;
@@ -169,15 +150,161 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
         const double phi = sq[lidx(kc, w, j + 3)];
         r = r + phi * (sf[fidx(NC, w, j + 1)] - sf[fidx(NC, w, j)]) / dx;
       }
+      double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
-      const double L = readR ? g.R[o] + r : r;
-      if (mode == OUT_PARTIAL || mode == OUT_RHS) {
+      if (MODE == OUT_PARTIAL || MODE == OUT_RHS) {
         g.Rout[o] = L;
       } else {
         const double h = *g.dt;
-        if (mode == OUT_RK1) {
+        if (MODE == OUT_RK1) {
           g.Uout[o] = g.U0[o] + h * L;
-        } else if (mode == OUT_RK2) {
+        } else if (MODE == OUT_RK2) {
+          g.Uout[o] = 0.75 * g.U0[o] + 0.25 * (g.Uin[o] + h * L);
+        } else {
+          g.Uout[o] = (1.0 / 3.0) * g.U0[o] + (2.0 / 3.0) * (g.Uin[o] + h * L);
+        }
+      }
+    }
+  }
+}
+
+// Learned-weights stage kernel (float32 reconstruction only): the same three
+// phases, but the face loop runs with every lane of the wave so that the
+// network's matrix instructions see the whole wave; lanes without a face
+// of their own evaluate face (0, 0) and store nothing.
+template <typename T, int NDIM, int D, int TL, int TW, int NTHR, int MODE, bool READ_R>
+__global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
+  constexpr int NC = 4 + NDIM;
+  constexpr int NP = TL + 6;     // staged positions along D
+  constexpr int NF = TL + 1;     // faces along D per tile row
+  constexpr int NWAVE = NTHR / 64;
+  // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
+  __shared__ double sq[NC * TW * NP];
+  __shared__ double sf[(NC + 1) * TW * NF];
+  __shared__ int s_status;
+  __shared__ int s_skip;
+  // learned weights: network + one inference tile per wave
+  __shared__ MlpLds mW[1];
+  __shared__ MlpInfTile mT[NWAVE];
+
+  const Geo<NDIM, D> geo(g.n);
+  const int64_t ntl = (geo.nL + TL - 1) / TL;
+  const int64_t bid = blockIdx.x;
+  const int64_t tl = bid % ntl;
+  const int64_t rest = bid / ntl;
+  const int64_t nta = (geo.nA + TW - 1) / TW;
+  const int64_t ta = rest % nta;
+  const int64_t tt = rest / nta;
+  const int64_t l0 = tl * TL, a0 = ta * TW;
+  const int64_t N = g.n[0] * g.n[1] * g.n[2];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_status = ST_OK;
+    // sticky failure: one read per workgroup so that all lanes agree
+    s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
+  }
+  mlp_stage_bf16(*mW, g.mlp, tid, NTHR);
+  __syncthreads();
+  if (s_skip) return;
+
+  auto lidx = [](int c, int w, int p) {
+    return D == 0 ? (c * TW + w) * NP + p : (c * NP + p) * TW + w;
+  };
+  auto fidx = [](int k, int w, int j) {
+    return D == 0 ? (k * TW + w) * NF + j : (k * NF + j) * TW + w;
+  };
+
+  // 1. stage primitives (FP64) with ghost cells
+  bool bad = false;
+  for (int e = tid; e < TW * NP; e += NTHR) {
+    const int w = D == 0 ? e / NP : e % TW;
+    const int p = D == 0 ? e % NP : e / TW;
+    const int64_t a = a0 + w;
+    const int64_t l = l0 + p - 3;
+    if (a >= geo.nA || l >= geo.nL + 3) continue;
+    bool flip;
+    const int64_t li = bc_index(l, geo.nL, g.bc_lo, g.bc_hi, flip);
+    const int64_t cell = a * geo.sA + li * geo.sL + tt * geo.sT;
+    double q[NC];
+    cell_prim<NDIM>(g.Uin, N, cell, q);
+    if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
+    if (flip) q[1 + D] = -q[1 + D];
+#pragma unroll
+    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = q[c];
+  }
+  if (bad) s_status = ST_NONPHYSICAL;
+  __syncthreads();
+
+  // 2. faces: the trip count is the same for every lane (see above)
+  int my3 = 0, my1 = 0;
+  MlpRun mr;
+  mr.W = mW;
+  mr.T = mT + (tid >> 6);
+  mr.thr = g.mlp_thr;
+  mr.fallbacks = 0;
+  for (int f0 = 0; f0 < TW * NF; f0 += NTHR) {
+    const int f = f0 + tid;
+    int w = D == 0 ? f / NF : f % TW;
+    int j = D == 0 ? f % NF : f / TW;
+    bool valid = f < TW * NF && a0 + w < geo.nA && l0 + j <= geo.nL;
+    if (!valid) {
+      w = 0;
+      j = 0;
+    }
+    LdsStencil st;
+    st.base = &sq[lidx(0, w, j)];
+    st.cstride = D == 0 ? TW * NP : NP * TW;
+    st.pstride = D == 0 ? 1 : TW;
+    double F[NC], us;
+    int n3, n1;
+    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, &mr);
+    if (!valid) continue;
+    // the face on a tile boundary is evaluated by both tiles; count it once
+    // (in the tile to its right, or the last tile for the domain's last face)
+    if (j < TL || l0 + j == geo.nL) {
+      my3 += n3;
+      my1 += n1;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
+    sf[fidx(NC, w, j)] = us;
+  }
+  if (g.stats) {
+    if (g.mood) {
+      if (my3) atomicAdd(&g.stats->o3[D], (unsigned long long)my3);
+      if (my1) atomicAdd(&g.stats->o1[D], (unsigned long long)my1);
+    }
+    if (mr.fallbacks) atomicAdd(&g.stats->mlp_fallback[D], (unsigned long long)mr.fallbacks);
+  }
+  __syncthreads();
+  if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
+
+  // 3. cells
+  const double dx = g.dx[D];
+  for (int e = tid; e < TW * TL; e += NTHR) {
+    const int w = D == 0 ? e / TL : e % TW;
+    const int j = D == 0 ? e % TL : e / TW;
+    const int64_t a = a0 + w;
+    const int64_t l = l0 + j;
+    if (a >= geo.nA || l >= geo.nL) continue;
+    const int64_t cell = a * geo.sA + l * geo.sL + tt * geo.sT;
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+      const int kc = axis_comp<NDIM, D>(k);
+      double r = -(sf[fidx(k, w, j + 1)] - sf[fidx(k, w, j)]) / dx;
+      if (k >= 3 + (NDIM - 1)) {
+        const double phi = sq[lidx(kc, w, j + 3)];
+        r = r + phi * (sf[fidx(NC, w, j + 1)] - sf[fidx(NC, w, j)]) / dx;
+      }
+      double L = READ_R ? g.R[kc * N + cell] + r : r;
+      const int64_t o = kc * N + cell;
+      if (MODE == OUT_PARTIAL || MODE == OUT_RHS) {
+        g.Rout[o] = L;
+      } else {
+        const double h = *g.dt;
+        if (MODE == OUT_RK1) {
+          g.Uout[o] = g.U0[o] + h * L;
+        } else if (MODE == OUT_RK2) {
           g.Uout[o] = 0.75 * g.U0[o] + 0.25 * (g.Uin[o] + h * L);
         } else {
           g.Uout[o] = (1.0 / 3.0) * g.U0[o] + (2.0 / 3.0) * (g.Uin[o] + h * L);
@@ -188,19 +315,13 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Time step: per-cell sum_d (|u_d| + c)/dx_d, a max per workgroup written to
-// partial[], then one workgroup takes the max of the partials and writes
-// dt = cfl / max (clipped to dt_max).  No atomics; the max does not depend on
-// the order, so dt is reproducible.
+// Time step: per-cell sum_d (|u_d| + c)/dx_d, block max, then a device-wide
+// max through an integer atomic on the (positive) double's bits.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double nanmax(double a, double b) {
-  return (b > a || b != b) ? b : a;
-}
-
 template <int NDIM>
 __global__ __launch_bounds__(256) void cfl_reduce_kernel(
     const double* U, int64_t n0, int64_t n1, int64_t n2, double dx0,
-    double dx1, double dx2, double* partial) {
+    double dx1, double dx2, unsigned long long* maxbits) {
   const int64_t N = n0 * n1 * n2;
   const double dxs[3] = {dx0, dx1, dx2};
   double m = 0.0;
@@ -212,35 +333,28 @@ __global__ __launch_bounds__(256) void cfl_reduce_kernel(
     double s = (fabs(q[1]) + cs) / dxs[0];
 #pragma unroll
     for (int a = 1; a < NDIM; a++) s = s + (fabs(q[1 + a]) + cs) / dxs[a];
-    m = nanmax(m, s);
+    m = (s > m || s != s) ? s : m;
   }
   __shared__ double red[256];
   red[threadIdx.x] = m;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + o]);
+    if (threadIdx.x < o) {
+      const double x = red[threadIdx.x + o];
+      if (x > red[threadIdx.x] || x != x) red[threadIdx.x] = x;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(red[0]));
 }
 
-__global__ __launch_bounds__(256) void cfl_finalize_kernel(const double* partial, int nblk,
-                                                           double cfl, double dt_max,
-                                                           double* dt) {
-  double m = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = nanmax(m, partial[b]);
-  __shared__ double red[256];
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = nanmax(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double h = cfl / red[0];
-    if (dt_max > 0.0 && h > dt_max) h = dt_max;
-    *dt = h;
-  }
+__global__ void cfl_finalize_kernel(unsigned long long* maxbits, double cfl,
+                                    double dt_max, double* dt) {
+  const double m = __longlong_as_double((long long)*maxbits);
+  double h = cfl / m;
+  if (dt_max > 0.0 && h > dt_max) h = dt_max;
+  *dt = h;
+  *maxbits = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -264,7 +378,7 @@ struct TileShape<NDIM, 2> {
   static constexpr int TL = 15, TW = 16;
 };
 
-template <typename T, int NDIM, int D, bool MLPW>
+template <typename T, int NDIM, int D, int MODE, bool READ_R, bool LEARNED>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s) {
   using TS = TileShape<NDIM, D>;
   constexpr int NTHR = 256;
@@ -276,57 +390,80 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s) {
   const int64_t blocks = ((nL + TS::TL - 1) / TS::TL) * ((nA + TS::TW - 1) / TS::TW) * nT;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MLPW>),
-                     dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
+  if constexpr (LEARNED)
+    hipLaunchKernelGGL((sweep_mlp_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                       dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                       dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool MLPW>
-static hipError_t launch_sweep_p(int ndim, int D, const SweepArgs& a, hipStream_t s) {
-  if (ndim == 1) return launch_sweep_t<T, 1, 0, MLPW>(a, s);
-  if (ndim == 2) {
-    return D == 0 ? launch_sweep_t<T, 2, 0, MLPW>(a, s) : launch_sweep_t<T, 2, 1, MLPW>(a, s);
+template <typename T, int NDIM, int D, bool LEARNED>
+static hipError_t launch_sweep_d(const SweepArgs& a, int mode, bool readR, hipStream_t s) {
+  switch (mode) {
+    case OUT_PARTIAL:
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_PARTIAL, true, LEARNED>(a, s)
+                   : launch_sweep_t<T, NDIM, D, OUT_PARTIAL, false, LEARNED>(a, s);
+    case OUT_RHS:
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RHS, true, LEARNED>(a, s)
+                   : launch_sweep_t<T, NDIM, D, OUT_RHS, false, LEARNED>(a, s);
+    case OUT_RK1:
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK1, true, LEARNED>(a, s)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK1, false, LEARNED>(a, s);
+    case OUT_RK2:
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK2, true, LEARNED>(a, s)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK2, false, LEARNED>(a, s);
+    default:
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK3, true, LEARNED>(a, s)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK3, false, LEARNED>(a, s);
   }
-  if (D == 0) return launch_sweep_t<T, 3, 0, MLPW>(a, s);
-  if (D == 1) return launch_sweep_t<T, 3, 1, MLPW>(a, s);
-  return launch_sweep_t<T, 3, 2, MLPW>(a, s);
 }
 
-hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a0, int mode,
-                        bool readR, hipStream_t s) {
-  SweepArgs a = a0;
-  a.mode = mode;
-  a.readR = readR ? 1 : 0;
-  if (a.weights == W_MLP) {
-    if (precision != 1 || !a.mlp) return hipErrorInvalidValue;
-    return launch_sweep_p<float, true>(ndim, D, a, s);
+template <typename T, bool LEARNED>
+static hipError_t launch_sweep_p(int ndim, int D, const SweepArgs& a, int mode, bool readR,
+                                 hipStream_t s) {
+  if (ndim == 1) return launch_sweep_d<T, 1, 0, LEARNED>(a, mode, readR, s);
+  if (ndim == 2) {
+    return D == 0 ? launch_sweep_d<T, 2, 0, LEARNED>(a, mode, readR, s)
+                  : launch_sweep_d<T, 2, 1, LEARNED>(a, mode, readR, s);
   }
-  return precision == 1 ? launch_sweep_p<float, false>(ndim, D, a, s)
-                        : launch_sweep_p<double, false>(ndim, D, a, s);
+  if (D == 0) return launch_sweep_d<T, 3, 0, LEARNED>(a, mode, readR, s);
+  if (D == 1) return launch_sweep_d<T, 3, 1, LEARNED>(a, mode, readR, s);
+  return launch_sweep_d<T, 3, 2, LEARNED>(a, mode, readR, s);
+}
+
+hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
+                        bool readR, hipStream_t s) {
+  if (a.weights == W_MLP) {
+    // learned weights: float32 reconstruction with a packed network only
+    if (precision != 1 || !a.mlp) return hipErrorInvalidValue;
+    return launch_sweep_p<float, true>(ndim, D, a, mode, readR, s);
+  }
+  return precision == 1 ? launch_sweep_p<float, false>(ndim, D, a, mode, readR, s)
+                        : launch_sweep_p<double, false>(ndim, D, a, mode, readR, s);
 }
 
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
-                      double cfl, double dt_max, double* partial, int max_partial,
-                      double* dt, int ncu, hipStream_t s) {
+                      double cfl, double dt_max, unsigned long long* maxbits, double* dt,
+                      int ncu, hipStream_t s) {
   const int64_t N = n[0] * n[1] * n[2];
   int64_t blocks = (N + 255) / 256;
-  int64_t cap = (int64_t)ncu * 4;
-  if (cap > max_partial) cap = max_partial;
+  const int64_t cap = (int64_t)ncu * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   if (ndim == 1)
     hipLaunchKernelGGL(cfl_reduce_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
   else if (ndim == 2)
     hipLaunchKernelGGL(cfl_reduce_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
   else
     hipLaunchKernelGGL(cfl_reduce_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], partial);
+                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(256), 0, s, partial, (int)blocks, cfl,
-                     dt_max, dt);
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, maxbits, cfl, dt_max, dt);
   return hipGetLastError();
 }
 

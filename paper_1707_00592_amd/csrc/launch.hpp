@@ -14,10 +14,10 @@ struct BatchArgs;
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
                         bool readR, hipStream_t s);
 
-// dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); partial is
-// device scratch of max_partial doubles.
+// dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); maxbits is
+// a zeroed device word, left zeroed on exit.
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
-                      double cfl, double dt_max, double* partial, int max_partial,
-                      double* dt, int ncu, hipStream_t s);
+                      double cfl, double dt_max, unsigned long long* maxbits, double* dt,
+                      int ncu, hipStream_t s);
 
 }  // namespace isw

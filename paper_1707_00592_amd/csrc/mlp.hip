@@ -10,7 +10,7 @@ namespace isw {
 
 constexpr int MLP_WAVES = 4;  // waves per workgroup in the training kernels
 
-// Per-sample loss and logit gradient (scaled by 1/n): soft cross-entropy of
+// Per-sample loss (unscaled) and logit gradient (scaled by 1/n): soft cross-entropy of
 // the two softmax heads against the target weights y[8] plus binary
 // cross-entropy of the confidence logit against c.
 // c < 0 asks for the confidence target to be formed here: 1 when both
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void mlp_grad_kernel(
         for (int k = 0; k < 9; k++) z[k] = T.z[l * 16 + k];
 #pragma unroll
         for (int k = 0; k < 8; k++) y[k] = Y[s * 8 + k];
-        loss += sample_loss(z, y, Cc ? Cc[s] : -1.0f, inv_n, dz);
+        loss += sample_loss(z, y, Cc ? Cc[s] : -1.0f, inv_n, dz) * inv_n;
       } else {
 #pragma unroll
         for (int k = 0; k < 9; k++) dz[k] = 0.0f;

@@ -52,8 +52,6 @@ struct SweepArgs {
   int bc_lo, bc_hi;    // of axis D
   int weights, mood;
   double eps;
-  int mode;            // OutMode of this launch
-  int readR;           // add the partial sum R of the previous axes
   const uint16_t* mlp; // packed bf16 network (learned weights only)
   float mlp_thr;
 };
