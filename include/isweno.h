@@ -160,7 +160,10 @@ ISWENO_API int isweno_cfl_dt(isweno_ctx *ctx, const isweno_grid *grid,
  *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
  *   U^{n+1} = 1/3 U + 2/3 (U2 + dt L(U2)).
  * dt is a device scalar: computed and written first when opts->cfl > 0,
- * read otherwise. */
+ * read otherwise.  The step's launches are captured once into a HIP graph
+ * per (U, dt, stats, grid, opts) and replayed on the given stream; with
+ * kernel timing enabled they are launched directly instead.  Same results
+ * either way. */
 ISWENO_API int isweno_rk3_step(isweno_ctx *ctx, const isweno_grid *grid,
                     const isweno_opts *opts, double *U, double *dt,
                     isweno_stats *stats, void *stream);
@@ -188,19 +191,27 @@ ISWENO_API int isweno_batch_autotune(isweno_ctx *ctx, isweno_batch_plan *plan,
 
 /* nsteps RK3 steps of every problem, in place.  dt: device [nprob]; with
  * opts->cfl > 0 each problem's dt is recomputed from its own cells at the
- * start of every step and written there, otherwise it is read.  Each step
- * is one HIP graph launch (per-problem dt reduction plus three persistent
- * stage kernels), instantiated on first use for this (plan, U, dt, stats,
- * opts) and replayed afterwards. */
+ * start of every step and written there, otherwise it is read.
+ * status: device int32 [nprob], required, sticky per problem: a problem is
+ * advanced only while its entry is ISWENO_OK (0).  A problem whose stage
+ * input has a non-finite or non-physical interior cell gets
+ * ISWENO_ERR_NONPHYSICAL; the step in which that is found is completed (its
+ * values are then unspecified) and the problem is not advanced afterwards,
+ * while the other problems go on.  stats (may be NULL) gets the MOOD
+ * counters and, when any problem failed, ISWENO_ERR_NONPHYSICAL.  Each step
+ * is one HIP graph launch (per-problem start-of-step kernel plus three
+ * persistent stage kernels), instantiated on first use for this (plan, U,
+ * dt, stats, status, opts) and replayed afterwards. */
 ISWENO_API int isweno_batch_step(isweno_ctx *ctx, isweno_batch_plan *plan,
                       const isweno_opts *opts, double *U, double *dt,
-                      int32_t nsteps, isweno_stats *stats, void *stream);
+                      int32_t nsteps, isweno_stats *stats, int32_t *status,
+                      void *stream);
 
 /* ---- learned weights (not in the paper) ----
  * A network 8 -> 32 -> 32 -> 9 (ReLU) replaces the nonlinear weights of
  * eq. (19): per face and characteristic field its input is the six
  * characteristic values of the stencil scaled to [0, 1] by their range
- * plus two material features, its output two softmax heads of four
+ * (all zero when the range is at most 1e-30) plus two material features, its output two softmax heads of four
  * weights (left and right face states) and a confidence logit.
  * Parameters are float32 masters, layout W1[32][8], b1[32], W2[32][32],
  * b2[32], W3[9][32], b3[9] (ISWENO_MLP_NPARAM floats). */
@@ -225,12 +236,15 @@ ISWENO_API int isweno_mlp_samples(isweno_ctx *ctx, const isweno_grid *grid,
 ISWENO_API int isweno_mlp_forward(isweno_ctx *ctx, const float *params, const float *X,
                        int64_t n, float *out, void *stream);
 
-/* Loss (soft cross-entropy of both heads against Y plus binary
- * cross-entropy of the confidence against C in {0,1}, averaged over n) and
- * its gradient w.r.t. the float32 parameters, from bf16 forward/backward
- * matrix-core kernels.  C may be NULL: the confidence target of a sample is
- * then 1 when both predicted heads are within 0.05 (L1 distance) of their
- * target weights and 0 otherwise.  loss: device float[1]; grad: device
+/* Loss, averaged over the n samples, and its gradient w.r.t. the float32
+ * parameters, from bf16 forward/backward matrix-core kernels.  Per side
+ * (left, right) the value the predicted weights give, applied to the
+ * candidates of eq. (20) on the sample's normalised stencil X[0..5] (left
+ * from X[0..4], right from the mirror X[5..1]), is compared with the value
+ * the target weights Y give: ((qhat - q) / 0.01)^2.  Plus binary
+ * cross-entropy of the confidence logit against C in {0,1}; C may be NULL:
+ * the label is then 1 when both |qhat - q| < 0.005 (units of the stencil's
+ * range) and 0 otherwise.  loss: device float[1]; grad: device
  * float[ISWENO_MLP_NPARAM] (overwritten).  Deterministic: the per-workgroup
  * partial sums are reduced in a fixed order. */
 ISWENO_API int isweno_mlp_loss_grad(isweno_ctx *ctx, const float *params, const float *X,

@@ -85,7 +85,8 @@ def load() -> C.CDLL:
     lib.or_rk3_step.argtypes = [C.POINTER(Grid), C.POINTER(Opts), _dp, C.c_double,
                                 C.POINTER(Stats)]
     lib.or_batch_step.argtypes = [C.c_int, C.POINTER(C.c_long), _dp, C.c_int, C.c_int,
-                                  C.POINTER(Opts), _dp, _dp, C.c_int, C.POINTER(Stats)]
+                                  C.POINTER(Opts), _dp, _dp, C.c_int, C.POINTER(Stats),
+                                  C.POINTER(C.c_int)]
     lib.or_exact_star.argtypes = [_dp, _dp, _dp, _dp]
     lib.or_exact_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     lib.or_mlp_forward.argtypes = [_dp, _dp, C.c_long, _dp]
@@ -233,18 +234,26 @@ def run(U, grid: Grid, opts: Opts, t_end: float | None = None, nsteps: int | Non
     return U, t, k, st
 
 
-def batch_step(U, offsets, dx, opts: Opts, dt=None, nsteps=1, bc_lo=0, bc_hi=0):
+def batch_step(U, offsets, dx, opts: Opts, dt=None, nsteps=1, bc_lo=0, bc_hi=0, pstatus=None):
+    """Returns (U, dt, stats, status) or, with pstatus (int array, updated in
+    place), (U, dt, stats, status, pstatus)."""
     U = _f64(U).copy()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     dxa = _f64(dx)
     nprob = len(dxa)
     dta = np.zeros(nprob) if dt is None else _f64(dt).copy()
     st = Stats()
+    ps = None
+    if pstatus is not None:
+        ps = np.ascontiguousarray(pstatus, dtype=np.intc).copy()
     s = load().or_batch_step(nprob, off.ctypes.data_as(C.POINTER(C.c_long)), _ptr(dxa),
                              int(bc_lo), int(bc_hi), C.byref(opts), _ptr(U), _ptr(dta),
-                             int(nsteps), C.byref(st))
+                             int(nsteps), C.byref(st),
+                             None if ps is None else ps.ctypes.data_as(C.POINTER(C.c_int)))
     if s == ERR_ARG:
         raise ValueError("oracle batch_step: bad arguments")
+    if ps is not None:
+        return U, dta, st, s, ps
     return U, dta, st, s
 
 
@@ -279,8 +288,10 @@ def mlp_forward(params, X):
     return out
 
 
-def mlp_loss_grad(params, X, Y, Cc):
-    params = _f64(params); X = _f64(X); Y = _f64(Y); Cc = _f64(Cc)
+def mlp_loss_grad(params, X, Y, Cc=None):
+    """Cc None: confidence labels formed from the value errors."""
+    params = _f64(params); X = _f64(X); Y = _f64(Y)
+    cp = None if Cc is None else _ptr(_f64(Cc))
     g = np.zeros(MLP_NPARAM)
-    loss = load().or_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(Y), _ptr(Cc), X.shape[0], _ptr(g))
+    loss = load().or_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(Y), cp, X.shape[0], _ptr(g))
     return loss, g

@@ -8,9 +8,12 @@
  *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3,
  *   left weights = softmax(z[0..3]), right weights = softmax(z[4..7]),
  *   confidence = sigmoid(z[8]).
- * Loss per sample: soft cross-entropy of each head against the target
- * weights plus binary cross-entropy of the confidence against its label.
- * Plain loops, no blocking; the gradient is the chain rule written out.
+ * Loss per sample: the squared error of the value each head reconstructs
+ * (its weights applied to the candidates of eq. (20) on the normalised
+ * stencil) against the value the target weights give, plus binary
+ * cross-entropy of the confidence against its label.  The candidates come
+ * from or_weno_candidates.  Plain loops, no blocking; the gradient is the
+ * chain rule written out.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -98,27 +101,39 @@ double or_mlp_loss_grad(const double *params, const double *X, const double *Y,
     forward1(&v, x, a1, h1, a2, h2, z);
     softmax4(z, pl);
     softmax4(z + 4, pr);
-    for (k = 0; k < 4; k++) {
-      loss -= y[k] * log(pl[k]) + y[4 + k] * log(pr[k]);
-      /* d(-sum y log softmax)/dz = softmax * sum(y) - y */
-    }
     {
-      double syl = 0.0, syr = 0.0;
+      /* candidates on the normalised stencil: left from x0..x4, right from
+       * the mirror image x5..x1 */
+      const double vl[5] = {x[0], x[1], x[2], x[3], x[4]};
+      const double vr[5] = {x[5], x[4], x[3], x[2], x[1]};
+      double cl[4], cr[4], qhl = 0.0, qhr = 0.0, qtl = 0.0, qtr = 0.0, el, er, c;
+      or_weno_candidates(vl, cl);
+      or_weno_candidates(vr, cr);
       for (k = 0; k < 4; k++) {
-        syl += y[k];
-        syr += y[4 + k];
+        qhl += pl[k] * cl[k];
+        qhr += pr[k] * cr[k];
+        qtl += y[k] * cl[k];
+        qtr += y[4 + k] * cr[k];
       }
+      el = (qhl - qtl) / OR_MLP_VALUE_SCALE;
+      er = (qhr - qtr) / OR_MLP_VALUE_SCALE;
+      loss += el * el + er * er;
+      /* d qhat / d z_k = p_k (c_k - qhat) (softmax Jacobian) */
       for (k = 0; k < 4; k++) {
-        dz[k] = pl[k] * syl - y[k];
-        dz[4 + k] = pr[k] * syr - y[4 + k];
+        dz[k] = 2.0 * el / OR_MLP_VALUE_SCALE * pl[k] * (cl[k] - qhl);
+        dz[4 + k] = 2.0 * er / OR_MLP_VALUE_SCALE * pr[k] * (cr[k] - qhr);
       }
-    }
-    {
-      const double zc = z[8], c = C[s];
-      const double sig = 1.0 / (1.0 + exp(-zc));
-      /* -[c log sig + (1-c) log(1-sig)], written stably */
-      loss += (zc > 0.0 ? zc : 0.0) - zc * c + log1p(exp(-fabs(zc)));
-      dz[8] = sig - c;
+      if (C)
+        c = C[s];
+      else
+        c = (fabs(qhl - qtl) < OR_MLP_CONF_TOL && fabs(qhr - qtr) < OR_MLP_CONF_TOL) ? 1.0 : 0.0;
+      {
+        const double zc = z[8];
+        const double sig = 1.0 / (1.0 + exp(-zc));
+        /* -[c log sig + (1-c) log(1-sig)], written stably */
+        loss += (zc > 0.0 ? zc : 0.0) - zc * c + log1p(exp(-fabs(zc)));
+        dz[8] = sig - c;
+      }
     }
     for (i = 0; i < NO; i++) dz[i] /= (double)n;
     for (i = 0; i < NO; i++) {

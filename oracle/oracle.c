@@ -557,10 +557,12 @@ int or_rk3_step(const or_grid *g, const or_opts *o, double *U, double dt,
 }
 
 /* Independent 1D problems stored back to back (each run with its own grid
- * spacing and time step). */
+ * spacing and time step).  A problem stops after the step in which its
+ * status became non-OK; pstatus (may be NULL) holds the per-problem status
+ * on entry (problems not OK are skipped) and on exit. */
 int or_batch_step(int nprob, const long *offsets, const double *dx, int bc_lo,
                   int bc_hi, const or_opts *o, double *U, double *dt,
-                  int nsteps, or_stats *st) {
+                  int nsteps, or_stats *st, int *pstatus) {
   if (nprob < 1 || !offsets || !dx || !o || !U || !dt || nsteps < 0)
     return OR_ERR_ARG;
   const long total = offsets[nprob];
@@ -572,7 +574,7 @@ int or_batch_step(int nprob, const long *offsets, const double *dx, int bc_lo,
     or_grid g;
     or_stats ls;
     double *Up = (double *)malloc(sizeof(double) * (size_t)(5 * n));
-    int c, step, s = OR_OK;
+    int c, step, s = pstatus ? pstatus[p] : OR_OK;
     long i;
     memset(&g, 0, sizeof(g));
     memset(&ls, 0, sizeof(ls));
@@ -593,6 +595,7 @@ int or_batch_step(int nprob, const long *offsets, const double *dx, int bc_lo,
       for (i = 0; i < n; i++) U[c * total + offsets[p] + i] = Up[c * n + i];
     o3 += ls.o3[0];
     o1 += ls.o1[0];
+    if (pstatus) pstatus[p] = s;
     if (s != OR_OK) {
 #pragma omp critical
       status = s;

@@ -109,10 +109,12 @@ int or_rk3_step(const or_grid *g, const or_opts *o, double *U, double dt,
  * back: U is [5][offsets[nprob]], problem p owns cells
  * offsets[p]..offsets[p+1]-1 with cell size dx[p].  If o->cfl > 0 each
  * problem's dt is recomputed every step and written to dt[p]; otherwise
- * dt[p] is used as given. */
+ * dt[p] is used as given.  A problem stops after the step in which its
+ * status became non-OK; pstatus (may be NULL) holds the per-problem status
+ * on entry (problems not OK are skipped) and on exit. */
 int or_batch_step(int nprob, const long *offsets, const double *dx, int bc_lo,
                   int bc_hi, const or_opts *o, double *U, double *dt,
-                  int nsteps, or_stats *st);
+                  int nsteps, or_stats *st, int *pstatus);
 
 /* ---- exact stiffened-gas Riemann problem (verification only) ----
  * W = (rho, u, p, gamma, Pinf). */
@@ -133,9 +135,16 @@ void or_exact_sample(const double WL[5], const double WR[5], double pstar,
    OR_MLP_NO * OR_MLP_H + OR_MLP_NO)
 void or_mlp_forward(const double *params, const double *X, long n,
                     double *logits);
-/* Loss = mean over samples of soft cross-entropy of both heads against
- * targets Y[n][8] plus binary cross-entropy of the confidence logit against
- * C[n] in {0,1}.  Writes the loss and its gradient w.r.t. params. */
+/* Loss = mean over samples of, per side h (left, right), the squared error
+ * ((qhat_h - q_h) / OR_MLP_VALUE_SCALE)^2 of the reconstructed value, where
+ * qhat_h = sum_k softmax(z_h)_k c_hk and q_h = sum_k Y_hk c_hk with c_hk the
+ * candidates of eq. (20) on the sample's normalised stencil X[0..5] (left
+ * side from X[0..4], right side from the mirror X[5..1]), plus binary
+ * cross-entropy of the confidence logit against its label: C[s], or when C
+ * is NULL, 1 where both |qhat_h - q_h| < OR_MLP_CONF_TOL, else 0.  Writes
+ * the loss and its gradient w.r.t. params. */
+#define OR_MLP_VALUE_SCALE 0.01
+#define OR_MLP_CONF_TOL 0.005
 double or_mlp_loss_grad(const double *params, const double *X, const double *Y,
                         const double *C, long n, double *grad);
 

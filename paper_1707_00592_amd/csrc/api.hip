@@ -1,7 +1,10 @@
 // C ABI of the WENO-IS library (declarations and contracts in isweno.h).
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "isweno.h"
@@ -24,6 +27,10 @@ struct isweno_ctx {
   std::vector<hipEvent_t> pool;
   double total_ms[ISWENO_K_COUNT] = {};
   int64_t launches[ISWENO_K_COUNT] = {};
+  // RK3 steps captured as HIP graphs, keyed by everything a captured step
+  // bakes in (pointers, grid, options, workspace)
+  hipStream_t cap = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -115,11 +122,18 @@ int check_opts(const isweno_opts* o) {
 
 int64_t ncells(const isweno_grid* g) { return g->n[0] * g->n[1] * g->n[2]; }
 
+void free_graphs(isweno_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 int ensure_ws(isweno_ctx* c, size_t bytes) {
   if (c->ws_bytes >= bytes) return ISWENO_OK;
   if (c->ws) {
-    // the old buffers may still be in use by queued work on any stream
+    // the old buffers may still be in use by queued work on any stream,
+    // and captured steps refer to them
     if (hipDeviceSynchronize() != hipSuccess) return ISWENO_ERR_DEVICE;
+    free_graphs(c);
     (void)hipFree(c->ws);
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -165,6 +179,48 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
   return hipSuccess;
 }
 
+// One RK3 step on stream s: the time step (when cfl > 0), then the three
+// stages.  Uses the workspace as U1 = ws, U2 = ws + nc*N.
+hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
+                       double* dt, isweno_stats* stats, hipStream_t s) {
+  const size_t sz = (size_t)(4 + g->ndim) * (size_t)ncells(g);
+  double* U1 = c->ws;
+  double* U2 = c->ws + sz;
+  hipError_t e;
+  if (o->cfl > 0.0) {
+    KTimer t(c, ISWENO_K_CFL, s);
+    if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt,
+                             c->ncu, s)) != hipSuccess)
+      return e;
+  }
+  isw::SweepArgs a = base_args(g, o, stats);
+  a.dt = dt;
+  a.U0 = U;
+  // stage 1: U1 = U + dt L(U)
+  a.Uin = U;
+  a.Uout = U1;
+  if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, s)) != hipSuccess) return e;
+  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+  a.Uin = U1;
+  a.Uout = U2;
+  if ((e = stage(c, g, o, a, U2, isw::OUT_RK2, s)) != hipSuccess) return e;
+  // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)); partial sums in U1
+  a.Uin = U2;
+  a.Uout = U;
+  return stage(c, g, o, a, U1, isw::OUT_RK3, s);
+}
+
+// Everything a captured RK3 step depends on (compared bytewise).
+struct StepKey {
+  const void* U;
+  const void* dt;
+  const void* stats;
+  const void* ws;
+  isweno_grid grid;
+  isweno_opts opts;
+};
+constexpr size_t kMaxGraphs = 64;
+
 }  // namespace
 
 extern "C" {
@@ -197,6 +253,8 @@ void isweno_destroy(isweno_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  free_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->ws) (void)hipFree(c->ws);
   if (c->maxbits) (void)hipFree(c->maxbits);
   drain_timing(c);
@@ -247,31 +305,51 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
   const int nc = 4 + g->ndim;
   const size_t sz = (size_t)nc * (size_t)N;
   if ((r = ensure_ws(c, 2 * sz * sizeof(double))) != ISWENO_OK) return r;
-  double* U1 = c->ws;
-  double* U2 = c->ws + sz;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (o->cfl > 0.0) {
-    KTimer t(c, ISWENO_K_CFL, s);
-    if (isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt, c->ncu, s) !=
-        hipSuccess)
+  // with kernel timing on, launch directly so that events bracket each
+  // kernel; otherwise replay the step's graph (captured on first use)
+  if (c->timing) return enqueue_rk3(c, g, o, U, dt, stats, s) == hipSuccess ? ISWENO_OK
+                                                                            : ISWENO_ERR_DEVICE;
+  StepKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.U = U;
+  k.dt = dt;
+  k.stats = stats;
+  k.ws = c->ws;
+  k.grid = *g;
+  k.opts = *o;
+  std::string key(reinterpret_cast<const char*>(&k), sizeof(k));
+  auto it = c->graphs.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != c->graphs.end()) {
+    exec = it->second;
+  } else {
+    if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+      c->cap = nullptr;
       return ISWENO_ERR_DEVICE;
+    }
+    if (c->graphs.size() >= kMaxGraphs) {
+      // bounded cache: the caller's streams may still run old graphs
+      if (hipDeviceSynchronize() != hipSuccess) return ISWENO_ERR_DEVICE;
+      free_graphs(c);
+    }
+    // capture on the context's own stream (the caller's may be the legacy
+    // default stream, which cannot be captured)
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return ISWENO_ERR_DEVICE;
+    const hipError_t e = enqueue_rk3(c, g, o, U, dt, stats, c->cap);
+    const hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ISWENO_ERR_DEVICE;
+    }
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return ISWENO_ERR_DEVICE;
+    c->graphs.emplace(std::move(key), exec);
   }
-  isw::SweepArgs a = base_args(g, o, stats);
-  a.dt = dt;
-  a.U0 = U;
-  // stage 1: U1 = U + dt L(U)
-  a.Uin = U;
-  a.Uout = U1;
-  if (stage(c, g, o, a, U1, isw::OUT_RK1, s) != hipSuccess) return ISWENO_ERR_DEVICE;
-  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-  a.Uin = U1;
-  a.Uout = U2;
-  if (stage(c, g, o, a, U2, isw::OUT_RK2, s) != hipSuccess) return ISWENO_ERR_DEVICE;
-  // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)); partial sums in U1
-  a.Uin = U2;
-  a.Uout = U;
-  if (stage(c, g, o, a, U1, isw::OUT_RK3, s) != hipSuccess) return ISWENO_ERR_DEVICE;
-  return ISWENO_OK;
+  return hipGraphLaunch(exec, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
 }
 
 int isweno_timing_enable(isweno_ctx* c, int enable) {

@@ -33,6 +33,8 @@ struct BatchArgs {
   const int64_t* tstart;   // first cell of each tile
   const int32_t* tprob;    // problem of each tile
   int64_t ntiles, total;
+  const int32_t* active;   // per problem: advanced in this step (set by the dt kernel)
+  int32_t* pstatus;        // per problem: sticky status
   StatsDev* stats;
   int bc_lo, bc_hi, weights, mood;
   double eps;
@@ -51,18 +53,18 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
   constexpr int NC = 5, NP = TL + 6, NF = TL + 1, NTHR = TL + 1;
   __shared__ double sq[NC * NP];
   __shared__ double sf[(NC + 1) * NF];
-  __shared__ int s_skip, s_status;
+  __shared__ int s_status;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_status = ST_OK;
-    s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
-  }
+  if (tid == 0) s_status = ST_OK;
   __syncthreads();
-  if (s_skip) return;
   const int64_t total = g.total;
   int my3 = 0, my1 = 0;
   for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
     const int prob = g.tprob[t];
+    // problems that were non-physical when this step began are frozen (the
+    // flag is written before the step's stages and not during them, so the
+    // branch is the same for every lane and every stage of the step)
+    if (!g.active[prob]) continue;
     const int64_t lo = g.offsets[prob], n = g.offsets[prob + 1] - lo;
     const int64_t l0 = g.tstart[t] - lo;
     const int len = (int)((n - l0) < TL ? (n - l0) : TL);
@@ -79,7 +81,10 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
 #pragma unroll
       for (int c = 0; c < NC; c++) sq[c * NP + p] = q[c];
     }
-    if (bad) s_status = ST_NONPHYSICAL;
+    if (bad) {
+      s_status = ST_NONPHYSICAL;
+      atomicExch(&g.pstatus[prob], (int32_t)ST_NONPHYSICAL);
+    }
     __syncthreads();
     for (int j = tid; j <= len; j += NTHR) {
       Lds1 st;
@@ -124,13 +129,20 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
   }
 }
 
-// Per-problem dt[p] = cfl / max_cells (|u| + c)/dx_p (clipped to dt_max):
-// one workgroup per problem.
+// Start of a step, one workgroup per problem: a problem is advanced in this
+// step when its status is still OK (active[p]); then, when cfl > 0,
+// dt[p] = cfl / max_cells (|u| + c)/dx_p (clipped to dt_max).  Frozen
+// problems keep their last dt.
 __global__ __launch_bounds__(256) void batch_dt_kernel(const double* U, int64_t total,
                                                        const int64_t* offsets,
                                                        const double* dx, double cfl,
-                                                       double dt_max, double* dt) {
+                                                       double dt_max, double* dt,
+                                                       const int32_t* pstatus,
+                                                       int32_t* active) {
   const int p = blockIdx.x;
+  const int act = pstatus[p] == ST_OK;
+  if (threadIdx.x == 0) active[p] = act;
+  if (!act || !(cfl > 0.0)) return;
   const int64_t lo = offsets[p], hi = offsets[p + 1];
   double m = 0.0;
   for (int64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
@@ -207,13 +219,15 @@ struct isweno_batch_plan {
   int64_t* offsets = nullptr;  // device
   double* dx = nullptr;        // device
   double* ws = nullptr;        // U1, U2 (device, 2 x 5 x total)
+  int32_t* active = nullptr;   // per problem, written at the start of each step
+  int32_t* tune_status = nullptr;  // per problem, for the autotuner's scratch runs
   std::map<int, TileTable> tables;  // by tile length
   int tl = 255;
   int blocks_per_cu = 4;
   hipStream_t cap = nullptr;   // capture stream
   // graph cache keyed by everything a captured step depends on
-  using Key = std::tuple<const void*, const void*, const void*, int, int, int, int, double, double,
-                         double, int, int>;
+  using Key = std::tuple<const void*, const void*, const void*, const void*, int, int, int,
+                         double, double, double, int, int>;
   std::map<Key, hipGraphExec_t> graphs;
   std::vector<int64_t> host_offsets;
 };
@@ -260,18 +274,21 @@ static int check_batch_opts(const isweno_opts* o) {
 
 // Enqueue one RK3 step (dt kernel + three persistent stages) on s.
 static hipError_t enqueue_step(isweno_batch_plan* p, const isweno_opts* o, double* U, double* dt,
-                               isweno_stats* stats, int tl, int bpc, hipStream_t s) {
+                               isweno_stats* stats, int32_t* pstatus, int tl, int bpc,
+                               hipStream_t s) {
   const TileTable& t = p->tables[tl];
   const int64_t sz = 5 * p->total;
   double* U1 = p->ws;
   double* U2 = p->ws + sz;
-  if (o->cfl > 0.0) {
+  {
     hipLaunchKernelGGL(isw::batch_dt_kernel, dim3(p->nprob), dim3(256), 0, s, U, p->total,
-                       p->offsets, p->dx, o->cfl, o->dt_max, dt);
+                       p->offsets, p->dx, o->cfl, o->dt_max, dt, pstatus, p->active);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   isw::BatchArgs a{};
+  a.active = p->active;
+  a.pstatus = pstatus;
   a.dt = dt;
   a.dx = p->dx;
   a.offsets = p->offsets;
@@ -334,6 +351,8 @@ int isweno_batch_plan_create(isweno_ctx* ctx, int32_t nprob, const int64_t* offs
   bool ok = hipMalloc(&p->offsets, sizeof(int64_t) * (nprob + 1)) == hipSuccess &&
             hipMalloc(&p->dx, sizeof(double) * nprob) == hipSuccess &&
             hipMalloc(&p->ws, sizeof(double) * 10 * p->total) == hipSuccess &&
+            hipMalloc(&p->active, sizeof(int32_t) * nprob) == hipSuccess &&
+            hipMalloc(&p->tune_status, sizeof(int32_t) * nprob) == hipSuccess &&
             hipMemcpy(p->offsets, offsets, sizeof(int64_t) * (nprob + 1),
                       hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(p->dx, dx, sizeof(double) * nprob, hipMemcpyHostToDevice) == hipSuccess &&
@@ -359,6 +378,8 @@ void isweno_batch_plan_destroy(isweno_batch_plan* p) {
   if (p->offsets) (void)hipFree(p->offsets);
   if (p->dx) (void)hipFree(p->dx);
   if (p->ws) (void)hipFree(p->ws);
+  if (p->active) (void)hipFree(p->active);
+  if (p->tune_status) (void)hipFree(p->tune_status);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   delete p;
 }
@@ -392,8 +413,9 @@ int isweno_batch_autotune(isweno_ctx* ctx, isweno_batch_plan* p, const isweno_op
       float ms_min = 1e30f;
       for (int rep = 0; rep < 3 && r == ISWENO_OK; rep++) {
         if (hipMemcpyAsync(S, U, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemsetAsync(p->tune_status, 0, sizeof(int32_t) * p->nprob, s) != hipSuccess ||
             hipEventRecord(e0, s) != hipSuccess ||
-            enqueue_step(p, &to, S, dt, nullptr, tl, bpc, s) != hipSuccess ||
+            enqueue_step(p, &to, S, dt, nullptr, p->tune_status, tl, bpc, s) != hipSuccess ||
             hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
           r = ISWENO_ERR_DEVICE;
           break;
@@ -424,15 +446,16 @@ int isweno_batch_autotune(isweno_ctx* ctx, isweno_batch_plan* p, const isweno_op
 }
 
 int isweno_batch_step(isweno_ctx* ctx, isweno_batch_plan* p, const isweno_opts* o, double* U,
-                      double* dt, int32_t nsteps, isweno_stats* stats, void* stream) {
+                      double* dt, int32_t nsteps, isweno_stats* stats, int32_t* status,
+                      void* stream) {
   int r;
-  if (!ctx || !p || !U || !dt || nsteps < 0) return ISWENO_ERR_ARG;
+  if (!ctx || !p || !U || !dt || !status || nsteps < 0) return ISWENO_ERR_ARG;
   if ((r = check_batch_opts(o)) != ISWENO_OK) return r;
   if (nsteps == 0) return ISWENO_OK;
   if (hipSetDevice(p->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  isweno_batch_plan::Key key{U, dt, stats, o->precision, o->weights, o->mood, 0, o->eps, o->cfl,
-                             o->dt_max, p->tl, p->blocks_per_cu};
+  isweno_batch_plan::Key key{U, dt, stats, status, o->precision, o->weights, o->mood, o->eps,
+                             o->cfl, o->dt_max, p->tl, p->blocks_per_cu};
   auto it = p->graphs.find(key);
   hipGraphExec_t exec = nullptr;
   if (it == p->graphs.end()) {
@@ -441,7 +464,8 @@ int isweno_batch_step(isweno_ctx* ctx, isweno_batch_plan* p, const isweno_opts* 
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return ISWENO_ERR_DEVICE;
-    const hipError_t e = enqueue_step(p, o, U, dt, stats, p->tl, p->blocks_per_cu, p->cap);
+    const hipError_t e =
+        enqueue_step(p, o, U, dt, stats, status, p->tl, p->blocks_per_cu, p->cap);
     const hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess || !graph) {
       if (graph) (void)hipGraphDestroy(graph);

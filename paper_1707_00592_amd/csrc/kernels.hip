@@ -322,18 +322,31 @@ template <int NDIM>
 __global__ __launch_bounds__(256) void cfl_reduce_kernel(
     const double* U, int64_t n0, int64_t n1, int64_t n2, double dx0,
     double dx1, double dx2, unsigned long long* maxbits) {
+  constexpr int NC = 4 + NDIM;
+  constexpr int UNR = 4;  // cells per lane and pass, loaded before any arithmetic
   const int64_t N = n0 * n1 * n2;
   const double dxs[3] = {dx0, dx1, dx2};
   double m = 0.0;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    double q[4 + NDIM];
-    cell_prim<NDIM>(U, N, c, q);
-    const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
-    double s = (fabs(q[1]) + cs) / dxs[0];
+  const int64_t span = (int64_t)blockDim.x * UNR;
+  for (int64_t c0 = blockIdx.x * span + threadIdx.x; c0 < N; c0 += (int64_t)gridDim.x * span) {
+    double u[UNR][NC];
 #pragma unroll
-    for (int a = 1; a < NDIM; a++) s = s + (fabs(q[1 + a]) + cs) / dxs[a];
-    m = (s > m || s != s) ? s : m;
+    for (int r = 0; r < UNR; r++) {
+      const int64_t c = c0 + (int64_t)r * blockDim.x;
+#pragma unroll
+      for (int k = 0; k < NC; k++) u[r][k] = c < N ? U[k * N + c] : 1.0;
+    }
+#pragma unroll
+    for (int r = 0; r < UNR; r++) {
+      if (c0 + (int64_t)r * blockDim.x >= N) continue;
+      double q[NC];
+      cons_prim<NDIM>(u[r], q);
+      const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
+      double s = (fabs(q[1]) + cs) / dxs[0];
+#pragma unroll
+      for (int a = 1; a < NDIM; a++) s = s + (fabs(q[1 + a]) + cs) / dxs[a];
+      m = (s > m || s != s) ? s : m;
+    }
   }
   __shared__ double red[256];
   red[threadIdx.x] = m;
@@ -448,8 +461,11 @@ hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double*
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
                       int ncu, hipStream_t s) {
   const int64_t N = n[0] * n[1] * n[2];
-  int64_t blocks = (N + 255) / 256;
-  const int64_t cap = (int64_t)ncu * 8;
+  int64_t blocks = (N + 1023) / 1024;
+  // one workgroup per CU: every workgroup ends in one atomic on the same
+  // word, and those serialise (measured: the kernel time grows by about
+  // 10 ns per workgroup)
+  const int64_t cap = (int64_t)ncu;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   if (ndim == 1)

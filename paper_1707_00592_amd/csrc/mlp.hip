@@ -10,38 +10,61 @@ namespace isw {
 
 constexpr int MLP_WAVES = 4;  // waves per workgroup in the training kernels
 
-// Per-sample loss (unscaled) and logit gradient (scaled by 1/n): soft cross-entropy of
-// the two softmax heads against the target weights y[8] plus binary
-// cross-entropy of the confidence logit against c.
-// c < 0 asks for the confidence target to be formed here: 1 when both
-// predicted heads are within 0.05 (L1) of their target weights, else 0.
-__device__ __forceinline__ float sample_loss(const float* z, const float* y, float c, float inv_n,
-                                             float* dz) {
-  float loss = 0.0f, dist = 0.0f;
+// Scale of the value error in the loss and tolerance of the confidence
+// label, in units of the stencil's range (the inputs are normalised to it).
+constexpr float kValueScale = 0.01f;
+constexpr float kConfTol = 0.005f;
+
+// Candidates of eq. (20) on a normalised stencil a..e = v_{i-2}..v_{i+2}.
+__device__ __forceinline__ void candidates(float a, float b, float c, float d, float e,
+                                           float* q) {
+  q[0] = 0.5f * c + 0.5f * d;
+  q[1] = -0.5f * b + 1.5f * c;
+  q[2] = (1.0f / 3.0f) * c + (5.0f / 6.0f) * d - (1.0f / 6.0f) * e;
+  q[3] = (1.0f / 3.0f) * a - (7.0f / 6.0f) * b + (11.0f / 6.0f) * c;
+}
+
+// Per-sample loss (unscaled) and logit gradient (scaled by 1/n).  Per side
+// h: qhat_h = sum_k softmax(z_h)_k c_hk, q_h = sum_k y_hk c_hk with c_hk the
+// candidates on the normalised stencil x (left from x0..x4, right from the
+// mirror x5..x1); loss ((qhat_h - q_h) / kValueScale)^2.  Plus binary
+// cross-entropy of the confidence logit against c; c < 0 asks for the
+// label to be formed here: 1 when both |qhat_h - q_h| < kConfTol, else 0.
+__device__ __forceinline__ float sample_loss(const float* z, const float* y, const float* x,
+                                             float c, float inv_n, float* dz) {
+  float loss = 0.0f, err = 0.0f;
 #pragma unroll
   for (int h = 0; h < 2; h++) {
     const float* zh = z + 4 * h;
+    float cand[4];
+    if (h == 0)
+      candidates(x[0], x[1], x[2], x[3], x[4], cand);
+    else
+      candidates(x[5], x[4], x[3], x[2], x[1], cand);
     float m = zh[0];
 #pragma unroll
     for (int k = 1; k < 4; k++) m = fmaxf(m, zh[k]);
-    float e[4], s = 0.0f, sy = 0.0f;
+    float e[4], s = 0.0f;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       e[k] = __expf(zh[k] - m);
       s += e[k];
-      sy += y[4 * h + k];
     }
-    const float lse = m + __logf(s);
-    float dh = 0.0f;
+    float qh = 0.0f, qt = 0.0f;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      loss -= y[4 * h + k] * (zh[k] - lse);
-      dz[4 * h + k] = (e[k] / s * sy - y[4 * h + k]) * inv_n;
-      dh += fabsf(e[k] / s - y[4 * h + k]);
+      e[k] = e[k] / s;
+      qh += e[k] * cand[k];
+      qt += y[4 * h + k] * cand[k];
     }
-    dist = fmaxf(dist, dh);
+    const float r = (qh - qt) * (1.0f / kValueScale);
+    loss += r * r;
+    err = fmaxf(err, fabsf(qh - qt));
+    const float g = 2.0f * r * (1.0f / kValueScale) * inv_n;
+#pragma unroll
+    for (int k = 0; k < 4; k++) dz[4 * h + k] = g * e[k] * (cand[k] - qh);
   }
-  if (c < 0.0f) c = dist < 0.05f ? 1.0f : 0.0f;
+  if (c < 0.0f) c = err < kConfTol ? 1.0f : 0.0f;
   const float zc = z[8];
   const float sig = 1.0f / (1.0f + __expf(-zc));
   loss += fmaxf(zc, 0.0f) - zc * c + log1pf(__expf(-fabsf(zc)));
@@ -83,12 +106,14 @@ __global__ __launch_bounds__(64 * MLP_WAVES) void mlp_grad_kernel(
       const int64_t s = s0 + l;
       float dz[9];
       if (s < n) {
-        float z[9], y[8];
+        float z[9], y[8], xs[MLP_NI];
 #pragma unroll
         for (int k = 0; k < 9; k++) z[k] = T.z[l * 16 + k];
 #pragma unroll
         for (int k = 0; k < 8; k++) y[k] = Y[s * 8 + k];
-        loss += sample_loss(z, y, Cc ? Cc[s] : -1.0f, inv_n, dz) * inv_n;
+#pragma unroll
+        for (int k = 0; k < MLP_NI; k++) xs[k] = X[s * MLP_NI + k];
+        loss += sample_loss(z, y, xs, Cc ? Cc[s] : -1.0f, inv_n, dz) * inv_n;
       } else {
 #pragma unroll
         for (int k = 0; k < 9; k++) dz[k] = 0.0f;

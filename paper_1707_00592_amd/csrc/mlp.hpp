@@ -158,8 +158,8 @@ __device__ __forceinline__ void mlp_material(double Gb, double Pb, float& f6, fl
 }
 
 // Network inputs for one characteristic field at one face: the six stencil
-// values scaled to [0, 1] by their range (all zero for a flat stencil) and
-// the two material inputs.
+// values scaled to [0, 1] by their range (all zero for a flat stencil, i.e.
+// a range of at most 1e-30) and the two material inputs.
 template <typename T>
 __device__ __forceinline__ void mlp_features(const T* w, float f6, float f7, float* x) {
   T lo = w[0], hi = w[0];
@@ -169,7 +169,9 @@ __device__ __forceinline__ void mlp_features(const T* w, float f6, float f7, flo
     hi = w[j] > hi ? w[j] : hi;
   }
   const T rng = hi - lo;
-  const float inv = rng > T(0) ? float(T(1) / rng) : 0.0f;
+  // ranges below 1e-30 count as flat: their reciprocal would overflow the
+  // float features (and 0 * inf gives NaN)
+  const float inv = rng > T(1e-30) ? float(T(1) / rng) : 0.0f;
 #pragma unroll
   for (int j = 0; j < 6; j++) x[j] = float(w[j] - lo) * inv;
   x[6] = f6;

@@ -83,24 +83,32 @@ __device__ __forceinline__ int64_t bc_index(int64_t l, int64_t n, int bclo,
 // Primitive recovery of one cell, axis order (rho, u_x.., p, Gamma, Pi),
 // eq. (2): p = (E - rho |u|^2 / 2 - Pi) / Gamma.
 template <int NDIM>
-__device__ __forceinline__ void cell_prim(const double* U, int64_t N,
-                                          int64_t cell, double* q) {
-  const double rho = U[cell];
+__device__ __forceinline__ void cons_prim(const double* u, double* q) {
+  const double rho = u[0];
   double vel[NDIM];
 #pragma unroll
-  for (int a = 0; a < NDIM; a++) vel[a] = U[(1 + a) * N + cell] / rho;
+  for (int a = 0; a < NDIM; a++) vel[a] = u[1 + a] / rho;
   double ke = vel[0] * vel[0];
 #pragma unroll
   for (int a = 1; a < NDIM; a++) ke = ke + vel[a] * vel[a];
-  const double E = U[(1 + NDIM) * N + cell];
-  const double G = U[(2 + NDIM) * N + cell];
-  const double P = U[(3 + NDIM) * N + cell];
+  const double E = u[1 + NDIM];
+  const double G = u[2 + NDIM];
+  const double P = u[3 + NDIM];
   q[0] = rho;
 #pragma unroll
   for (int a = 0; a < NDIM; a++) q[1 + a] = vel[a];
   q[1 + NDIM] = (E - 0.5 * rho * ke - P) / G;
   q[2 + NDIM] = G;
   q[3 + NDIM] = P;
+}
+
+template <int NDIM>
+__device__ __forceinline__ void cell_prim(const double* U, int64_t N,
+                                          int64_t cell, double* q) {
+  double u[4 + NDIM];
+#pragma unroll
+  for (int k = 0; k < 4 + NDIM; k++) u[k] = U[k * N + cell];
+  cons_prim<NDIM>(u, q);
 }
 
 template <int NDIM>
@@ -186,8 +194,12 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
                                       MlpRun* mr = nullptr) {
   constexpr int NT = NDIM - 1, NC = 5 + NT;
   constexpr int CR = 0, CU = 1 + D, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
-#pragma unroll 1
+  // Fully unrolled over the fields (static register indices for the face
+  // states, no loop-carried copies); the scheduling barrier keeps the
+  // compiler from interleaving fields, which bounds register pressure.
+#pragma unroll
   for (int m = 0; m < NC; m++) {
+    __builtin_amdgcn_sched_barrier(0);
     // row of L: 0 = acoustic (sign sa), 1 = entropy, 2 = copy of component cx
     int kind = 2, cx = CG;
     T sa = a;

@@ -61,7 +61,8 @@ _SIGS = {
     "isweno_batch_plan_destroy": (None, [_vp]),
     "isweno_batch_autotune": (C.c_int, [_vp, _vp, C.POINTER(Opts), _vp,
                                         C.POINTER(C.c_int32), _vp]),
-    "isweno_batch_step": (C.c_int, [_vp, _vp, C.POINTER(Opts), _vp, _vp, C.c_int32, _vp, _vp]),
+    "isweno_batch_step": (C.c_int, [_vp, _vp, C.POINTER(Opts), _vp, _vp, C.c_int32, _vp, _vp,
+                                    _vp]),
     "isweno_mlp_samples": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp,
                                      C.c_int64, C.c_int64, _vp, _vp]),
     "isweno_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp]),
@@ -258,6 +259,19 @@ class BatchPlan:
             "batch_plan_create")
         self._h = h
         self.ctx = ctx
+        self._status = None
+
+    @property
+    def status(self):
+        """Per-problem status (device int32 [nprob], sticky; 0 = OK) used by
+        step() when no status array is passed."""
+        import torch
+        if self._status is None:
+            self._status = torch.zeros(self.nprob, dtype=torch.int32, device="cuda")
+        return self._status
+
+    def reset_status(self):
+        self.status.zero_()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -276,9 +290,11 @@ class BatchPlan:
                                            C.byref(tile), _stream()), "batch_autotune")
         return tile.value
 
-    def step(self, U, opts: Opts, dt, nsteps: int = 1, stats=None):
+    def step(self, U, opts: Opts, dt, nsteps: int = 1, stats=None, status=None):
+        st = self.status if status is None else status
         check(load().isweno_batch_step(self.ctx.handle, self._h, C.byref(opts), _ptr(U), _ptr(dt),
-                                       int(nsteps), _ptr(stats), _stream()), "batch_step")
+                                       int(nsteps), _ptr(stats), _ptr(st), _stream()),
+              "batch_step")
         return U
 
 

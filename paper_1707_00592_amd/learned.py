@@ -3,9 +3,17 @@
 Data: face samples that the method itself generates.  Plain WENO-IS runs of
 given problems are snapshotted and isweno_mlp_samples turns every face and
 characteristic field into 8 network inputs plus the eq. (28) weights of both
-sides (the targets).  Samples whose weights differ from the optimal d_k by
-more than 0.05 somewhere are kept whole; the near-linear rest is thinned so
-that they make up a stated share.
+sides (the targets).  Samples whose candidate values (eq. (20), on the
+normalised stencil) spread by more than 0.05 of the stencil's range on a
+side, where the weights decide the result, are kept whole; the rest, where
+any convex weights give nearly the same value, is thinned so that the former
+make up a stated share.
+
+Loss: the error of the value the predicted weights reconstruct against the
+value of the target weights (both on the same candidates), plus a
+confidence head trained to say whether that error is below 0.005 of the
+stencil's range; in the solver, faces below the confidence threshold use the
+eq. (28) weights.
 
 Training: full-precision float32 master parameters, bf16 matrix-core
 forward and backward (isweno_mlp_loss_grad), Adam (isweno_mlp_adam), all in
@@ -18,9 +26,6 @@ import math
 import numpy as np
 
 from . import isweno
-
-D_OPT = np.array([0.4, 0.2, 0.3, 0.1] * 2, dtype=np.float32)
-
 
 def init_params(seed: int = 1707) -> np.ndarray:
     """He-uniform weights, zero biases; the confidence bias starts at +2."""
@@ -58,13 +63,28 @@ def collect(ctx: isweno.Context, problems, opts: isweno.Opts, steps: int, every:
     return torch.cat(Xs), torch.cat(Ys)
 
 
-def stratify(X, Y, share_nontrivial: float = 0.3, seed: int = 1707, limit: int | None = None):
-    """Keeps every sample whose weights depart from d_k by more than 0.05 and
-    enough of the others that the former are `share_nontrivial` of the set
-    (or all of them if there are too few near-linear samples)."""
+def candidates(X):
+    """Candidates of eq. (20) of both sides on the normalised stencils
+    X[:, 0..5]: returns (left [n,4], right [n,4])."""
     import torch
-    d = torch.from_numpy(D_OPT).to(Y.device)
-    nontriv = (Y - d).abs().amax(dim=1) > 0.05
+
+    def c4(a, b, c, d, e):
+        return torch.stack([0.5 * c + 0.5 * d, -0.5 * b + 1.5 * c,
+                            c / 3.0 + 5.0 * d / 6.0 - e / 6.0,
+                            a / 3.0 - 7.0 * b / 6.0 + 11.0 * c / 6.0], dim=1)
+    x = X
+    return (c4(x[:, 0], x[:, 1], x[:, 2], x[:, 3], x[:, 4]),
+            c4(x[:, 5], x[:, 4], x[:, 3], x[:, 2], x[:, 1]))
+
+
+def stratify(X, Y, share_nontrivial: float = 0.3, seed: int = 1707, limit: int | None = None):
+    """Keeps every sample whose candidates spread by more than 0.05 on a side
+    and enough of the others that the former are `share_nontrivial` of the
+    set (or all of them if there are too few of the others)."""
+    import torch
+    cl, cr = candidates(X)
+    spread = torch.maximum(cl.amax(1) - cl.amin(1), cr.amax(1) - cr.amin(1))
+    nontriv = spread > 0.05
     gen = torch.Generator(device="cpu").manual_seed(seed)
     idx_n = torch.nonzero(nontriv).flatten().cpu()
     idx_t = torch.nonzero(~nontriv).flatten().cpu()
@@ -107,13 +127,21 @@ def train(ctx: isweno.Context, X, Y, steps: int = 2000, batch: int = 65536, lr: 
     return P, hist
 
 
-def evaluate(ctx: isweno.Context, P, X, Y):
-    """Mean loss and the mean L1 distance of the predicted weights on a set."""
+def evaluate(ctx: isweno.Context, P, X, Y, conf_threshold: float = 0.5):
+    """Value error of the predicted weights on a set (units of the stencil's
+    range): its mean, the share of samples within 0.005 on both sides, the
+    share the confidence head accepts, and the share of accepted samples
+    that are within 0.005 (precision of the confidence head)."""
     import torch
     out = torch.empty((X.shape[0], 9), dtype=torch.float32, device="cuda")
     ctx.mlp_forward(P, X, out)
     pl = torch.softmax(out[:, :4], dim=1); pr = torch.softmax(out[:, 4:8], dim=1)
-    dist = torch.maximum((pl - Y[:, :4]).abs().sum(1), (pr - Y[:, 4:]).abs().sum(1))
-    conf = torch.sigmoid(out[:, 8])
-    return {"mean_l1": float(dist.mean()), "frac_within_0.05": float((dist < 0.05).float().mean()),
-            "frac_confident": float((conf >= 0.5).float().mean())}
+    cl, cr = candidates(X)
+    el = ((pl - Y[:, :4]) * cl).sum(1).abs()
+    er = ((pr - Y[:, 4:]) * cr).sum(1).abs()
+    err = torch.maximum(el, er)
+    ok = err < 0.005
+    conf = torch.sigmoid(out[:, 8]) >= conf_threshold
+    acc = float((ok & conf).float().sum() / conf.float().sum().clamp(min=1.0))
+    return {"mean_value_err": float(err.mean()), "frac_within_0.005": float(ok.float().mean()),
+            "frac_confident": float(conf.float().mean()), "confident_precision": acc}

@@ -331,6 +331,14 @@ def batch_riemann(nprob: int = 4096, seed: int = 1707, nmin: int = 128, nmax: in
             if not _cavitates(side[0], side[1]):
                 break
         sizes.append(n); states.append(tuple(side)); x0s.append(x0)
+    return batch_from_states(sizes, states, x0s)
+
+
+def batch_from_states(sizes, states, x0s):
+    """Shock tubes on [0, 1] stored back to back: problem k has sizes[k]
+    cells (dx = 1/N), the states ((rho, u, p, gamma, pinf) left, right) =
+    states[k] and its interface at x0s[k]."""
+    nprob = len(sizes)
     offsets = np.zeros(nprob + 1, dtype=np.int64)
     offsets[1:] = np.cumsum(sizes)
     total = int(offsets[-1])
@@ -344,7 +352,7 @@ def batch_riemann(nprob: int = 4096, seed: int = 1707, nmin: int = 128, nmax: in
             arr[sl] = np.where(left, WL[idx], WR[idx])
     U = prim_to_cons(rho, [u], p, ga, pi)
     dx = 1.0 / np.asarray(sizes, dtype=np.float64)
-    return {"U": U, "offsets": offsets, "dx": dx, "states": states, "x0": np.asarray(x0s),
+    return {"U": U, "offsets": offsets, "dx": dx, "states": list(states), "x0": np.asarray(x0s),
             "sizes": np.asarray(sizes)}
 
 

@@ -130,6 +130,45 @@ def test_full_size_batch_sampled(lib, ctx):
         np.testing.assert_array_equal(got[:, off[k]:off[k + 1]], ref[:, sub_off[i]:sub_off[i + 1]])
 
 
+def test_failing_problem_is_frozen_and_the_others_go_on(lib, ctx):
+    """Per-problem status: a tube that turns non-physical (a mild pressure
+    step between light and very heavy air; fails in its 7th step at CFL 0.5,
+    the oracle as well) is frozen after that step while its neighbours are
+    advanced; statuses and the other problems match the oracle bit for bit,
+    also across a second call that continues from the sticky statuses."""
+    import torch
+    bad = ((1.2160491579263077, 3.3501146997202227, 2310231.7121894024, 1.4, 0.0),
+           (870.6981057699048, 77.33057448129418, 6633397.388649134, 1.4, 0.0))
+    good = wl.batch_riemann(4, seed=11, nmin=100, nmax=400)
+    sizes = [int(good["sizes"][0]), 975, int(good["sizes"][1]), int(good["sizes"][2])]
+    states = [good["states"][0], bad, good["states"][1], good["states"][2]]
+    x0s = [good["x0"][0], 0.44847387793766924, good["x0"][1], good["x0"][2]]
+    b = wl.batch_from_states(sizes, states, x0s)
+    o = oracle.make_opts(mood=True, cfl=0.5)
+    ref, dtr, _, s, ps = oracle.batch_step(b["U"], b["offsets"], b["dx"], o, nsteps=5,
+                                           pstatus=np.zeros(4, dtype=np.intc))
+    assert s == 0 and list(ps) == [0, 0, 0, 0]
+    ref, dtr, _, s, ps = oracle.batch_step(ref, b["offsets"], b["dx"], o, dt=dtr, nsteps=7,
+                                           pstatus=ps)
+    assert list(ps) == [0, oracle.ERR_NONPHYSICAL, 0, 0]
+    plan = ctx.batch_plan(b["offsets"], b["dx"])
+    U = _dev(b["U"])
+    dt = torch.zeros(4, dtype=torch.float64, device="cuda")
+    stats = lib.new_stats()
+    opts = lib.make_opts(mood=True, cfl=0.5)
+    plan.step(U, opts, dt, nsteps=5, stats=stats)
+    assert plan.status.cpu().tolist() == [0, 0, 0, 0]
+    plan.step(U, opts, dt, nsteps=7, stats=stats)
+    assert plan.status.cpu().tolist() == [0, lib.ERR_NONPHYSICAL, 0, 0]
+    assert lib.read_stats(stats).status == lib.ERR_NONPHYSICAL
+    got = U.cpu().numpy()
+    off = b["offsets"]
+    for k in (0, 2, 3):
+        np.testing.assert_array_equal(got[:, off[k]:off[k + 1]], ref[:, off[k]:off[k + 1]])
+    np.testing.assert_array_equal(dt.cpu().numpy()[[0, 2, 3]], dtr[[0, 2, 3]])
+    print("[batch] frozen problem 1, others bitwise over 12 steps", flush=True)
+
+
 def test_plan_argument_errors(lib, ctx):
     with pytest.raises(RuntimeError, match="invalid argument"):
         ctx.batch_plan(np.array([0, 5, 5]), np.array([0.1, 0.1]))      # empty problem

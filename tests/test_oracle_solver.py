@@ -336,6 +336,19 @@ def test_mlp_gradient_matches_finite_differences():
         Pm = P.copy(); Pm[i] -= h
         fd = (oracle.mlp_loss_grad(Pp, X, Y, Cc)[0] - oracle.mlp_loss_grad(Pm, X, Y, Cc)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+    # a network whose heads output the target weights exactly (zero weights,
+    # biases log y) reconstructs the target values: only the confidence
+    # term remains, log 2 per sample at a zero confidence logit
+    y = np.array([0.1, 0.2, 0.3, 0.4, 0.25, 0.25, 0.4, 0.1])
+    P0 = np.zeros(oracle.MLP_NPARAM)
+    P0[-9:-1] = np.log(y)
+    l0, g0 = oracle.mlp_loss_grad(P0, X, np.tile(y, (7, 1)), Cc)
+    assert l0 == pytest.approx(np.log(2.0), rel=1e-14)
+    # value term: uniform heads on a linear stencil give every candidate the
+    # same value, so any target weights give zero value error too
+    Xl = np.tile(np.array([0.0, 0.2, 0.4, 0.6, 0.8, 1.0, 0.3, 0.1]), (7, 1))
+    l1, _ = oracle.mlp_loss_grad(np.zeros(oracle.MLP_NPARAM), Xl, Y, Cc)
+    assert l1 == pytest.approx(np.log(2.0), rel=1e-12)
     # forward heads: softmax of the logits
     z = oracle.mlp_forward(P, X)
     assert z.shape == (7, 9)
