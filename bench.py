@@ -92,9 +92,10 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--extras", default="",
-                    help="other workloads to report: 3d (256^3 shock-droplet), batch "
-                         "(4096 uneven tubes), mlp (learned weights); empty for none")
+    ap.add_argument("--extras", default="mlp,accuracy,3d,batch",
+                    help="other workloads to report: mlp (learned weights, trained here), "
+                         "accuracy (every form against a 2x finer FP64 run), 3d (256^3 "
+                         "shock-droplet), batch (4096 uneven tubes); empty for none")
     return ap.parse_args()
 
 
@@ -184,7 +185,8 @@ def extra_batch(isweno, workloads, ctx, torch, steps=100):
 def extra_mlp(isweno, workloads, ctx, torch, steps=300):
     """Learned weights: trained on the GPU on faces of plain runs of the
     gas-liquid shock tube and the 3D shock-droplet (at 96^3), then run on
-    the 2D shock-bubble at 2048 x 1024 next to the FP64 and FP32 forms."""
+    the 2D shock-bubble at 2048 x 1024 next to the FP64 and FP32 forms.
+    Returns (report, packed network)."""
     from paper_1707_00592_amd import learned
     t0 = time.perf_counter()
     opts64 = isweno.make_opts()
@@ -203,8 +205,7 @@ def extra_mlp(isweno, workloads, ctx, torch, steps=300):
     U2 = torch.from_numpy(p2.U).to("cuda")
     forms = {"fp64": isweno.make_opts(),
              "fp32": isweno.make_opts(precision=isweno.FP32),
-             "mlp": isweno.make_opts(precision=isweno.FP32, weights=isweno.W_MLP,
-                                     mlp_params=packed, mlp_conf_threshold=0.5)}
+             "mlp": learned_opts(isweno, packed)}
     out = {"workload": "2D shock-bubble 2048x1024, MOOD on, CFL 0.5", "steps": steps}
     res = {}
     for name, o in forms.items():
@@ -224,6 +225,53 @@ def extra_mlp(isweno, workloads, ctx, torch, steps=300):
                        "seconds": round(train_s, 1), "loss": hist, **ev}
     del res, U2
     torch.cuda.empty_cache()
+    return out, packed
+
+
+def learned_opts(isweno, packed):
+    return isweno.make_opts(precision=isweno.FP32, weights=isweno.W_MLP, mlp_params=packed,
+                            mlp_conf_threshold=0.5)
+
+
+def pressure(U):
+    """p = (E - rho |u|^2 / 2 - Pi) / Gamma of a 2D state [6][N]."""
+    rho = U[0]
+    ke = 0.5 * (U[1] * U[1] + U[2] * U[2]) / rho
+    return (U[3] - ke - U[5]) / U[4]
+
+
+def equal_l1(isweno, workloads, ctx, torch, forms, values, nsteps=1000):
+    """Each form on the 1024x512 shock-bubble to the time the FP64 path
+    reaches in `nsteps` steps, against the FP64 path at 2048x1024 averaged
+    over 2x2 blocks: L1 of rho and p per form, and whether it lies within 5%
+    of the FP64 form's L1 (the condition under which the speed-ups are
+    quoted at equal error)."""
+    p = workloads.shock_bubble_2d(1024, 512)
+    g = isweno.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    U = torch.from_numpy(p.U).to("cuda")
+    _, t_end, _ = isweno.Solver(g, forms["fp64"], ctx).run(U.clone(), nsteps=nsteps, t_end=1.0)
+    pr = workloads.shock_bubble_2d(2048, 1024)
+    gr = isweno.make_grid(pr.n, pr.dx, pr.bc_lo, pr.bc_hi)
+    Ur = torch.from_numpy(pr.U).to("cuda")
+    isweno.Solver(gr, forms["fp64"], ctx).run(Ur, t_end=t_end)
+    ref = Ur.view(6, 512, 2, 1024, 2).mean(dim=(2, 4)).reshape(6, -1)
+    del Ur
+    pref = pressure(ref)
+    out = {"t_end": t_end, "reference": "FP64 path at 2048x1024, 2x2 block averages"}
+    for name, o in forms.items():
+        Uf = U.clone()
+        isweno.Solver(g, o, ctx).run(Uf, t_end=t_end)
+        out[name] = {"l1_rho": float((Uf[0] - ref[0]).abs().mean() / ref[0].abs().mean()),
+                     "l1_p": float((pressure(Uf) - pref).abs().mean() / pref.abs().mean())}
+        if name in values:
+            out[name]["value"] = values[name]
+    base = out["fp64"]
+    for name in forms:
+        f = out[name]
+        f["equal_l1"] = bool(abs(f["l1_rho"] - base["l1_rho"]) <= 0.05 * base["l1_rho"] and
+                             abs(f["l1_p"] - base["l1_p"]) <= 0.05 * base["l1_p"])
+        if "value" in f and "value" in base:
+            f["speedup_vs_fp64"] = f["value"] / base["value"]
     return out
 
 
@@ -376,12 +424,39 @@ def main():
     extras = [e.strip() for e in args.extras.split(",") if e.strip()]
     out["forms"] = forms_out
     other = {}
+    packed = None
     if "mlp" in extras:
-        other["learned_weights"] = extra_mlp(isweno, workloads, ctx, torch)
+        try:
+            other["learned_weights"], packed = extra_mlp(isweno, workloads, ctx, torch)
+            o = learned_opts(isweno, packed)
+            _, el, _, st, _ = run_form(isweno, ctx, p, U0, o, min(args.steps, 300), 5, torch, 5)
+            forms_out["mlp"] = {"value": cells_stages / args.steps * min(args.steps, 300) / el,
+                                "status": st.status}
+            forms_out["mlp"]["speedup_vs_fp64"] = forms_out["mlp"]["value"] / value
+        except Exception as e:  # report, keep the contract line
+            other["learned_weights"] = {"error": repr(e)}
+    if "accuracy" in extras:
+        try:
+            fo = {"fp64": isweno.make_opts(), "fp32": isweno.make_opts(precision=isweno.FP32)}
+            vals = {"fp64": value}
+            if "fp32" in forms_out:
+                vals["fp32"] = forms_out["fp32"]["value"]
+            if packed is not None:
+                fo["mlp"] = learned_opts(isweno, packed)
+                vals["mlp"] = forms_out["mlp"]["value"]
+            other["equal_l1_1024x512"] = equal_l1(isweno, workloads, ctx, torch, fo, vals)
+        except Exception as e:
+            other["equal_l1_1024x512"] = {"error": repr(e)}
     if "3d" in extras:
-        other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)
+        try:
+            other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)
+        except Exception as e:
+            other["shock_droplet_3d"] = {"error": repr(e)}
     if "batch" in extras:
-        other["batch_riemann"] = extra_batch(isweno, workloads, ctx, torch)
+        try:
+            other["batch_riemann"] = extra_batch(isweno, workloads, ctx, torch)
+        except Exception as e:
+            other["batch_riemann"] = {"error": repr(e)}
     if other:
         out["other_workloads"] = other
     if not args.no_cpu:

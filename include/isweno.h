@@ -162,8 +162,8 @@ ISWENO_API int isweno_cfl_dt(isweno_ctx *ctx, const isweno_grid *grid,
  * dt is a device scalar: computed and written first when opts->cfl > 0,
  * read otherwise.  The step's launches are captured once into a HIP graph
  * per (U, dt, stats, grid, opts) and replayed on the given stream; with
- * kernel timing enabled they are launched directly instead.  Same results
- * either way. */
+ * kernel timing enabled, or with opts->dt_max > 0, they are launched
+ * directly instead.  Same results either way. */
 ISWENO_API int isweno_rk3_step(isweno_ctx *ctx, const isweno_grid *grid,
                     const isweno_opts *opts, double *U, double *dt,
                     isweno_stats *stats, void *stream);

@@ -306,10 +306,12 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
   const size_t sz = (size_t)nc * (size_t)N;
   if ((r = ensure_ws(c, 2 * sz * sizeof(double))) != ISWENO_OK) return r;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  // with kernel timing on, launch directly so that events bracket each
-  // kernel; otherwise replay the step's graph (captured on first use)
-  if (c->timing) return enqueue_rk3(c, g, o, U, dt, stats, s) == hipSuccess ? ISWENO_OK
-                                                                            : ISWENO_ERR_DEVICE;
+  // Launch directly with kernel timing on (events bracket each kernel) and
+  // when dt is clipped (dt_max > 0: a value that usually changes from call
+  // to call, and a graph per value would only be captured to be dropped);
+  // otherwise replay the step's graph (captured on first use).
+  if (c->timing || o->dt_max > 0.0)
+    return enqueue_rk3(c, g, o, U, dt, stats, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
   StepKey k;
   std::memset(&k, 0, sizeof(k));
   k.U = U;
