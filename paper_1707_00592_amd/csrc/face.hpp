@@ -126,6 +126,96 @@ __device__ __forceinline__ double weno_f64(double a, double b, double c,
          (al.a4 / sum) * c4;
 }
 
+// ---------------------------------------------------------------------------
+// The same FP64 reconstruction with cheaper divisions and identical bits.
+//
+// An IEEE double division x / y is computed on this hardware as: operand
+// scaling (only for extreme exponents), an approximate reciprocal r of y,
+// two Newton steps r += r (1 - y r), q = x r, one residual correction
+// q += r (x - y q) (Markstein's method, all steps fused multiply-adds), and a
+// special-value fix-up.  When no scaling can occur and no operand is special
+// the scaling and fix-up steps return their inputs, so the five fused steps
+// alone give the correctly rounded quotient, bit for bit.  Divisions by the
+// same y then also share r: the four omega_k = alpha_k / sum(alpha) need one
+// reciprocal instead of four.
+//
+// Range that guarantees it here: epsilon in [2^-200, 2^100], every indicator
+// finite with their sum at most 2^200, and tau either 0 or at least 2^-700.
+// Then every denominator lies in [2^-200, 2^201], every nonzero quotient and
+// every alpha in [2^-901, 2^801], no residual is subnormal, and sum(alpha)
+// is at least 0.1.  Lanes outside the range redo the reconstruction with the
+// plain divisions (weno_f64).
+// ---------------------------------------------------------------------------
+struct Recip {
+  double y, r;
+};
+
+__device__ __forceinline__ Recip recip(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  double e = __builtin_fma(-y, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-y, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return {y, r};
+}
+
+__device__ __forceinline__ double divide(double x, const Recip& d) {
+  const double q = x * d.r;
+  const double rem = __builtin_fma(-d.y, q, x);
+  return __builtin_fma(rem, d.r, q);
+}
+
+__device__ __forceinline__ bool fast_division_range(const Ind<double>& s) {
+  const double sum = ((((s.tau + s.b1) + s.b2) + s.b3) + s.b4) + s.b12;
+  return sum <= 0x1p200 && (s.tau == 0.0 || s.tau >= 0x1p-700);
+}
+
+__device__ __forceinline__ double weno_f64_shared_recip(const Ind<double>& s, double a, double b,
+                                                       double c, double d, double e,
+                                                       int weights, double eps, bool order3) {
+  Alpha al;
+  if (weights == W_BASIC) {
+    al.a1 = ISW_D1 * (1.0 + divide(s.tau, recip(s.b1 + eps)));
+    al.a2 = ISW_D2 * (1.0 + divide(s.tau, recip(s.b2 + eps)));
+    al.a3 = ISW_D3 * (1.0 + divide(s.tau, recip(s.b3 + eps)));
+    al.a4 = ISW_D4 * (1.0 + divide(s.tau, recip(s.b4 + eps)));
+  } else {
+    const double r12 = divide(s.tau, recip(s.b12 + eps));
+    al.a1 = ISW_D1 * (1.0 + divide(s.tau, recip(s.b1 + eps)) * r12);
+    al.a2 = ISW_D2 * (1.0 + divide(s.tau, recip(s.b2 + eps)) * r12);
+    al.a3 = order3 ? 0.0 : ISW_D3 * (1.0 + divide(s.tau, recip(s.b3 + eps)));
+    al.a4 = order3 ? 0.0 : ISW_D4 * (1.0 + divide(s.tau, recip(s.b4 + eps)));
+  }
+  if (order3) {
+    al.a3 = 0.0;
+    al.a4 = 0.0;
+  }
+  const double sum = ((al.a1 + al.a2) + al.a3) + al.a4;
+  const Recip rs = recip(sum);
+  const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+  const double c2 = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+  if (order3) {
+    return divide(al.a1, rs) * c1 + divide(al.a2, rs) * c2;
+  }
+  const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+  const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+  return ((divide(al.a1, rs) * c1 + divide(al.a2, rs) * c2) + divide(al.a3, rs) * c3) +
+         divide(al.a4, rs) * c4;
+}
+
+// FP64 reconstruction as used by the stage kernels: the shared-reciprocal
+// form, recomputed with the plain divisions (weno_f64) on the lanes outside
+// its range (a divergent branch that a wave skips when no lane needs it).
+__device__ __forceinline__ double weno_f64_fast(double a, double b, double c, double d,
+                                                double e, int weights, double eps,
+                                                bool order3) {
+  const Ind<double> s = indicators<double>(a, b, c, d, e);
+  double q = weno_f64_shared_recip(s, a, b, c, d, e, weights, eps, order3);
+  if (!(eps >= 0x1p-200 && eps <= 0x1p100 && fast_division_range(s)))
+    q = weno_f64(a, b, c, d, e, weights, eps, order3);
+  return q;
+}
+
 // Eq. (19) in FP32.  The indicators grow with the square of the data and
 // the modified weights multiply two ratios, which overflows float for the
 // pressure-like fields (|q| up to 1e9).  The stencil is therefore shifted by
@@ -178,7 +268,7 @@ template <>
 __device__ __forceinline__ double weno<double>(double a, double b, double c,
                                                double d, double e, int w,
                                                double eps, bool o3) {
-  return weno_f64(a, b, c, d, e, w, eps, o3);
+  return weno_f64_fast(a, b, c, d, e, w, eps, o3);
 }
 template <>
 __device__ __forceinline__ float weno<float>(float a, float b, float c,

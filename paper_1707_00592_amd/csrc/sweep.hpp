@@ -233,6 +233,7 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       if (!(sides & (1 << side))) continue;
+      __builtin_amdgcn_sched_barrier(0);
       double* q = side ? qr : ql;
       const double r =
           learned ? double(side ? rrm : rlm)
