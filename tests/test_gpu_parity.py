@@ -228,6 +228,50 @@ def test_full_size_rhs_matches_oracle(lib, ctx):
     _check(got, ref, what="rhs 1024x512")
 
 
+def test_full_size_2048x1024_rhs_matches_oracle(lib, ctx):
+    """The 2048 x 1024 shock-bubble grid of the learned-weights workload,
+    one FP64 evaluation after two steps, bit for bit."""
+    torch = _torch()
+    p = wl.shock_bubble_2d(2048, 1024)
+    og, ig = _grids(p)
+    U = _dev(p.U)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        ctx.rk3_step(U, ig, lib.make_opts(), dt)
+    Uh = U.cpu().numpy()
+    ref, _ = oracle.rhs(Uh, og, oracle.make_opts())
+    got = ctx.rhs(U, ig, lib.make_opts()).cpu().numpy()
+    _check(got, ref, what="rhs 2048x1024")
+
+
+def test_full_size_3d_droplet_rhs_matches_oracle(lib, ctx):
+    """The 256^3 shock-droplet grid: one FP64 evaluation bit for bit against
+    the oracle, and the FP32 form of the same evaluation within its bound.
+    Most of this grid is at rest, so several reference components are zero
+    almost everywhere and their own L1 cannot normalise the FP32 rounding;
+    the FP32 bound is instead on the change one CFL time step makes to the
+    state: sum |L32 - L64| dt / sum |U| per component (momenta against the
+    momentum magnitude) below 1e-6."""
+    p = wl.shock_droplet_3d(256)
+    og, ig = _grids(p)
+    o = oracle.make_opts()
+    ref, _ = oracle.rhs(p.U, og, o)
+    dt = oracle.cfl_dt(p.U, og, o)
+    mom = np.sqrt(p.U[1] ** 2 + p.U[2] ** 2 + p.U[3] ** 2).sum()
+    scale = np.array([np.abs(p.U[0]).sum(), mom, mom, mom, np.abs(p.U[4]).sum(),
+                      np.abs(p.U[5]).sum(), np.abs(p.U[6]).sum()])
+    U = _dev(p.U)
+    del p
+    got = ctx.rhs(U, ig, lib.make_opts()).cpu().numpy()
+    _check(got, ref, what="rhs 256^3")
+    del got
+    g32 = ctx.rhs(U, ig, lib.make_opts(precision=lib.FP32)).cpu().numpy()
+    e = np.abs(g32 - ref).sum(axis=1) * dt / scale
+    print(f"[parity] rhs 256^3 FP32 form: per-step state change error {np.array2string(e, precision=2)}",
+          flush=True)
+    assert np.all(np.isfinite(g32)) and e.max() < 1e-6
+
+
 def test_graph_replays_match_direct_launches(lib, ctx):
     """isweno_rk3_step replays one captured HIP graph per (pointers, grid,
     options); with kernel timing on it launches directly.  Several replays
