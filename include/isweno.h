@@ -236,6 +236,15 @@ ISWENO_API int isweno_mlp_samples(isweno_ctx *ctx, const isweno_grid *grid,
 ISWENO_API int isweno_mlp_forward(isweno_ctx *ctx, const float *params, const float *X,
                        int64_t n, float *out, void *stream);
 
+/* Inference exactly as the stage kernel runs it (isweno_opts.weights =
+ * ISWENO_W_MLP): packed bf16 parameters (isweno_mlp_pack), activations kept
+ * in registers, bf16 matrix-core layers with float32 accumulation, 64
+ * samples per wavefront.  X: device float [n][8]; out: device float [n][9]
+ * logits.  For users who cannot run the whole solver and for checking the
+ * solver's network against the float32 one. */
+ISWENO_API int isweno_mlp_infer(isweno_ctx *ctx, const uint16_t *packed, const float *X,
+                     int64_t n, float *out, void *stream);
+
 /* Loss, averaged over the n samples, and its gradient w.r.t. the float32
  * parameters, from bf16 forward/backward matrix-core kernels.  Per side
  * (left, right) the value the predicted weights give, applied to the

@@ -177,7 +177,6 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   constexpr int NC = 4 + NDIM;
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
-  constexpr int NWAVE = NTHR / 64;
   // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
   __shared__ double sq[NC * TW * NP];
   __shared__ double sf[(NC + 1) * TW * NF];
@@ -185,7 +184,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   __shared__ int s_skip;
   // learned weights: network + one inference tile per wave
   __shared__ MlpLds mW[1];
-  __shared__ MlpInfTile mT[NWAVE];
+  __shared__ MlpBiasLds mB[1];
 
   const Geo<NDIM, D> geo(g.n);
   const int64_t ntl = (geo.nL + TL - 1) / TL;
@@ -204,6 +203,10 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
     s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
   }
   mlp_stage_bf16(*mW, g.mlp, tid, NTHR);
+  __syncthreads();
+  mlp_bias_stage(*mB, *mW, tid, NTHR);
+  MlpRegs regs;
+  mlp_regs_load(*mW, regs);
   __syncthreads();
   if (s_skip) return;
 
@@ -238,8 +241,8 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   // 2. faces: the trip count is the same for every lane (see above)
   int my3 = 0, my1 = 0;
   MlpRun mr;
-  mr.W = mW;
-  mr.T = mT + (tid >> 6);
+  mr.R = &regs;
+  mr.B = mB;
   mr.thr = g.mlp_thr;
   mr.fallbacks = 0;
   for (int f0 = 0; f0 < TW * NF; f0 += NTHR) {

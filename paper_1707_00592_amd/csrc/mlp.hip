@@ -214,6 +214,31 @@ __global__ void mlp_reduce_kernel(const float* part, int nblk, float* grad, floa
     *loss = s;
 }
 
+// The network as the stage kernel evaluates it (packed bf16 parameters,
+// activations in registers, 64 samples per wave): one sample per lane,
+// lanes past n evaluate zeros and store nothing.
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const uint16_t* packed, const float* X,
+                                                       int64_t n, float* out) {
+  __shared__ MlpLds W;
+  __shared__ MlpBiasLds B;
+  const int tid = threadIdx.x;
+  mlp_stage_bf16(W, packed, tid, 256);
+  __syncthreads();
+  mlp_bias_stage(B, W, tid, 256);
+  MlpRegs R;
+  mlp_regs_load(W, R);
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * 256 + tid;
+  float x[MLP_NI], z[MLP_NO];
+#pragma unroll
+  for (int k = 0; k < MLP_NI; k++) x[k] = s < n ? X[s * MLP_NI + k] : 0.0f;
+  mlp_logits_wave(x, R, B, z);
+  if (s < n) {
+#pragma unroll
+    for (int k = 0; k < MLP_NO; k++) out[s * MLP_NO + k] = z[k];
+  }
+}
+
 __global__ __launch_bounds__(64 * MLP_WAVES) void mlp_forward_kernel(const float* P,
                                                                      const float* X, int64_t n,
                                                                      float* out) {
@@ -385,6 +410,18 @@ int isweno_mlp_samples(isweno_ctx* ctx, const isweno_grid* g, const isweno_opts*
   if (hipMemcpyAsync(count, &written, sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess)
     return ISWENO_ERR_DEVICE;
   return hipStreamSynchronize(s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
+}
+
+int isweno_mlp_infer(isweno_ctx* ctx, const uint16_t* packed, const float* X, int64_t n,
+                     float* out, void* stream) {
+  if (!ctx || !packed || !X || !out || n < 0) return ISWENO_ERR_ARG;
+  if (n == 0) return ISWENO_OK;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffLL) return ISWENO_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(isw::mlp_infer_kernel, dim3((unsigned)blocks), dim3(256), 0, s, packed, X, n,
+                     out);
+  return hipGetLastError() == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
 }
 
 int isweno_mlp_forward(isweno_ctx* ctx, const float* P, const float* X, int64_t n, float* out,

@@ -112,15 +112,123 @@ __device__ __forceinline__ void mlp_tile_forward(const MlpLds& W, MlpTile& T) {
   mlp_forward32(W, T.x, T.h1, T.h2, T.z);
 }
 
-// Per-wave scratch for inference inside the stage kernel (z over h1).
-struct MlpInfTile {
-  uint16_t x[32 * MLP_NI];
-  uint16_t h2[32 * MLP_H];
-  union {
-    uint16_t h1[32 * MLP_H];
-    float z[32 * 16];
-  };
+// ---------------------------------------------------------------------------
+// Inference inside the stage kernel, activations in registers.
+//
+// Layers are computed transposed, h^T = W x^T, so that the 32 samples of a
+// tile are the columns: lane l then holds, for sample l % 32, the output
+// rows 8 (r / 4) + 4 (l / 32) + r % 4 in accumulator r, which are exactly the
+// K entries 8 q + 4 (l / 32) + t (q = r / 4, t = r % 4) that it has to supply
+// as the B operand of the next layer's q-th 8-wide slice.  Only the network
+// inputs (and the logits) cross between the two halves of the wave.
+// ---------------------------------------------------------------------------
+
+// A operands of the three layers as lane l supplies them: row l % 32,
+// K entries 4 (l / 32) + t of every 8-wide slice (W3 rows 9..31 are zero).
+struct MlpRegs {
+  bf16x4 w1, w2[4], w3[4];
 };
+
+// Biases in LDS, arranged as the accumulator registers of each wave half.
+struct alignas(16) MlpBiasLds {
+  float b[3][2][16];
+};
+
+__device__ __forceinline__ void mlp_regs_load(const MlpLds& W, MlpRegs& R) {
+  const int l = threadIdx.x & 63, i = l & 31, kh = (l >> 5) * 4;
+#pragma unroll
+  for (int t = 0; t < 4; t++) R.w1[t] = (short)W.w1[i * MLP_NI + kh + t];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      R.w2[q][t] = (short)W.w2[i * MLP_H + 8 * q + kh + t];
+      R.w3[q][t] = (short)W.w3[i * MLP_H + 8 * q + kh + t];
+    }
+  }
+}
+
+// Whole workgroup, after W is staged; the caller synchronises.
+__device__ __forceinline__ void mlp_bias_stage(MlpBiasLds& B, const MlpLds& W, int tid, int nthr) {
+  for (int e = tid; e < 3 * 2 * 16; e += nthr) {
+    const int layer = e / 32, half = (e / 16) & 1, r = e & 15;
+    const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+    B.b[layer][half][r] = layer == 0 ? W.b1[row] : (layer == 1 ? W.b2[row] : W.b3[row]);
+  }
+}
+
+__device__ __forceinline__ f32x16 mlp_bias_acc(const MlpBiasLds& B, int layer) {
+  const int half = (threadIdx.x & 63) >> 5;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; r++) acc[r] = B.b[layer][half][r];
+  return acc;
+}
+
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// Four floats to bf16 (round to nearest even, the hardware conversion).
+__device__ __forceinline__ bf16x4 pack_bf16x4(float a, float b, float c, float d) {
+  const bf16x2v lo = __builtin_convertvector((f32x2){a, b}, bf16x2v);
+  const bf16x2v hi = __builtin_convertvector((f32x2){c, d}, bf16x2v);
+  i32x2 u;
+  u[0] = __builtin_bit_cast(int, lo);
+  u[1] = __builtin_bit_cast(int, hi);
+  return __builtin_bit_cast(bf16x4, u);
+}
+
+// max(x, 0) in one integer instruction: negative floats (sign bit set) are
+// negative as integers, non-negative ones keep their order.
+__device__ __forceinline__ float relu(float x) {
+  const int i = __builtin_bit_cast(int, x);
+  return __builtin_bit_cast(float, i > 0 ? i : 0);
+}
+
+// One 32-sample tile: xb is this lane's layer-1 B operand (inputs
+// 4 (l / 32) + t of sample l % 32).  Returns the layer-3 accumulators:
+// lanes 0..31 hold logits 0..3 (r = 0..3) and 8 (r = 4) of sample l, lanes
+// 32..63 logits 4..7 (r = 0..3) of sample l - 32.
+__device__ __forceinline__ f32x16 mlp_tile_regs(const MlpRegs& R, const MlpBiasLds& B,
+                                                bf16x4 xb) {
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 acc = mlp_bias_acc(B, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(R.w1, xb, acc, 0, 0, 0);
+  bf16x4 h[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+    h[q] = pack_bf16x4(relu(acc[4 * q]), relu(acc[4 * q + 1]), relu(acc[4 * q + 2]),
+                       relu(acc[4 * q + 3]));
+  acc = mlp_bias_acc(B, 1);
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(R.w2[q], h[q], acc, 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+    h[q] = pack_bf16x4(relu(acc[4 * q]), relu(acc[4 * q + 1]), relu(acc[4 * q + 2]),
+                       relu(acc[4 * q + 3]));
+  acc = mlp_bias_acc(B, 2);
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(R.w3[q], h[q], acc, 0, 0, 0);
+  return acc;
+}
+
+
+// Exchange with the lane 32 apart (the other half of the wave).
+__device__ __forceinline__ bf16x4 shfl_xor32(bf16x4 v);
+
+// Logits z[9] of this lane's sample x[8]: the 64 samples of the wave run as
+// two 32-sample tiles (every lane must call; tile 0 holds the samples of
+// lanes 0..31, tile 1 those of lanes 32..63).
+__device__ __forceinline__ void mlp_logits_wave(const float* x, const MlpRegs& R,
+                                                const MlpBiasLds& B, float* z);
+
+__device__ __forceinline__ bf16x4 shfl_xor32(bf16x4 v) {
+  i32x2 u = __builtin_bit_cast(i32x2, v);
+  u[0] = __shfl_xor(u[0], 32);
+  u[1] = __shfl_xor(u[1], 32);
+  return __builtin_bit_cast(bf16x4, u);
+}
 
 // Stage float32 master parameters into LDS (whole workgroup; caller syncs).
 __device__ __forceinline__ void mlp_stage_f32(MlpLds& W, const float* P, int tid, int nthr) {
@@ -178,10 +286,45 @@ __device__ __forceinline__ void mlp_features(const T* w, float f6, float f7, flo
   x[7] = f7;
 }
 
+__device__ __forceinline__ void mlp_logits_wave(const float* x, const MlpRegs& R,
+                                                const MlpBiasLds& B, float* z) {
+  const bool upper = (threadIdx.x & 32) != 0;
+  const bf16x4 lo = pack_bf16x4(x[0], x[1], x[2], x[3]);
+  const bf16x4 hi = pack_bf16x4(x[4], x[5], x[6], x[7]);
+  // tile 0 needs inputs 4..7 of the lower lanes' samples from the upper
+  // lanes, tile 1 inputs 0..3 of the upper lanes' samples from the lower ones
+  const bf16x4 recv = shfl_xor32(upper ? lo : hi);
+  // only accumulators 0..4 of each tile are used (the rest die at once)
+  float t0[5], t1[5];
+  {
+    const f32x16 a = mlp_tile_regs(R, B, upper ? recv : lo);
+#pragma unroll
+    for (int k = 0; k < 5; k++) t0[k] = a[k];
+  }
+  {
+    const f32x16 a = mlp_tile_regs(R, B, upper ? hi : recv);
+#pragma unroll
+    for (int k = 0; k < 5; k++) t1[k] = a[k];
+  }
+  // lower lanes own logits 0..3 and 8 of tile 0 and hold those of tile 1's
+  // samples; upper lanes own logits 4..7 of tile 1 and hold those of tile 0's
+  float sendv[5], got[5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) sendv[k] = upper ? (k < 4 ? t0[k] : 0.0f) : t1[k];
+#pragma unroll
+  for (int k = 0; k < 5; k++) got[k] = __shfl_xor(sendv[k], 32);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    z[k] = upper ? got[k] : t0[k];
+    z[4 + k] = upper ? t1[k] : got[k];
+  }
+  z[8] = upper ? got[4] : t0[4];
+}
+
 // Learned-weights state of one wave inside the stage kernel.
 struct MlpRun {
-  const MlpLds* W;
-  MlpInfTile* T;
+  const MlpRegs* R;
+  const MlpBiasLds* B;
   float thr;       // confidence threshold (sigmoid of the last logit)
   float f6, f7;    // material inputs of the current face
   int fallbacks;   // face-fields that used the eq. (28) weights instead

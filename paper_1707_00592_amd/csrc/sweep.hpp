@@ -138,30 +138,15 @@ __device__ __host__ constexpr int axis_comp(int k) {
 // field's column of R (eq. (13)) into the face states in field order.
 // sides: bit 0 = left, bit 1 = right.  S(c, j) reads LDS component c (axis
 // order) at stencil position j.
-// Learned weights for one field: both sides' weights from the network
-// (two 32-row passes of the wave's tile), the candidates of eq. (20) and
-// eq. (19); below the confidence threshold the eq. (28) weights are used.
+// Learned weights for one field: the network on the 64 faces of the wave
+// (two 32-sample tiles, all lanes take part), its weights applied to the
+// candidates of eq. (20) as in eq. (19); below the confidence threshold the
+// eq. (28) weights are used instead.
 template <typename T>
 __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, T& rr) {
-  const int l = threadIdx.x & 63;
   float x[8], z[9];
   mlp_features<T>(w, mr.f6, mr.f7, x);
-#pragma unroll
-  for (int h = 0; h < 2; h++) {
-    if ((l >> 5) == h) {
-#pragma unroll
-      for (int k = 0; k < 8; k++) mr.T->x[(l & 31) * 8 + k] = f2bf(x[k]);
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    mlp_forward32(*mr.W, mr.T->x, mr.T->h1, mr.T->h2, mr.T->z);
-    if ((l >> 5) == h) {
-#pragma unroll
-      for (int k = 0; k < 9; k++) z[k] = mr.T->z[(l & 31) * 16 + k];
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-  }
+  mlp_logits_wave(x, *mr.R, *mr.B, z);
   const float conf = 1.0f / (1.0f + __expf(-z[8]));
   if (!(conf >= mr.thr)) {
     rl = weno<T>(w[0], w[1], w[2], w[3], w[4], W_MODIFIED, eps, false);
@@ -179,12 +164,18 @@ __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, 
       e[k] = __expf(zs[k] - m);
       sum += e[k];
     }
-    const T A = side ? w[5] : w[0], B = side ? w[4] : w[1], C = side ? w[3] : w[2],
-            D_ = side ? w[2] : w[3], E = side ? w[1] : w[4];
-    const T c1 = (C + D_) / T(2), c2 = (T(3) * C - B) / T(2);
-    const T c3 = (T(2) * C + T(5) * D_ - E) / T(6), c4 = (T(2) * A - T(7) * B + T(11) * C) / T(6);
-    const T q = (T(e[0]) * c1 + T(e[1]) * c2 + T(e[2]) * c3 + T(e[3]) * c4) / T(sum);
-    if (side) rr = q; else rl = q;
+    const float A = float(side ? w[5] : w[0]), B = float(side ? w[4] : w[1]),
+                C = float(side ? w[3] : w[2]), D_ = float(side ? w[2] : w[3]),
+                E = float(side ? w[1] : w[4]);
+    // candidates of eq. (20) written as the centre value plus differences,
+    // so that a constant stencil is reproduced exactly; weighted and
+    // normalised by one reciprocal
+    const float d1 = 0.5f * (D_ - C), d2 = 0.5f * (C - B);
+    const float d3 = (5.0f / 6.0f) * (D_ - C) - (1.0f / 6.0f) * (E - C);
+    const float d4 = (1.0f / 3.0f) * (A - C) - (7.0f / 6.0f) * (B - C);
+    const float q =
+        C + (e[0] * d1 + e[1] * d2 + e[2] * d3 + e[3] * d4) * __builtin_amdgcn_rcpf(sum);
+    if (side) rr = T(q); else rl = T(q);
   }
 }
 

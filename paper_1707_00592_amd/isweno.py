@@ -66,6 +66,7 @@ _SIGS = {
     "isweno_mlp_samples": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp,
                                      C.c_int64, C.c_int64, _vp, _vp]),
     "isweno_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp]),
+    "isweno_mlp_infer": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp]),
     "isweno_mlp_loss_grad": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "isweno_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_float, C.c_float,
                                   C.c_float, C.c_float, _vp]),
@@ -225,6 +226,12 @@ class Context:
     def mlp_forward(self, params, X, out):
         check(load().isweno_mlp_forward(self._h, _ptr(params), _ptr(X), int(X.shape[0]),
                                         _ptr(out), _stream()), "mlp_forward")
+        return out
+
+    def mlp_infer(self, packed, X, out):
+        """Logits as the solver's stage kernel computes them (packed network)."""
+        check(load().isweno_mlp_infer(self._h, _ptr(packed), _ptr(X), int(X.shape[0]),
+                                      _ptr(out), _stream()), "mlp_infer")
         return out
 
     def mlp_loss_grad(self, params, X, Y, Cc, loss, grad):

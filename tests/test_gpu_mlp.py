@@ -56,6 +56,32 @@ def test_forward_matches_reference(lib, ctx):
     assert err.max() < 3e-2
 
 
+def test_solver_inference_matches_reference(lib, ctx):
+    """The network as the stage kernel runs it (packed bf16 parameters,
+    activations in registers, two 32-sample tiles per wavefront) against the
+    FP64 network on the bf16-rounded parameters and inputs, over several
+    waves and a ragged tail; and against the float32-master forward kernel."""
+    import torch
+    rs = np.random.default_rng(7)
+    P = _params(7)
+    n = 64 * 9 + 37
+    X = rs.uniform(0, 1, size=(n, 8)).astype(np.float32)
+    packed = torch.zeros(oracle.MLP_NPARAM, dtype=torch.int16, device="cuda")
+    ctx.mlp_pack(_dev(P), packed)
+    out = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    ctx.mlp_infer(packed, _dev(X), out)
+    got = out.cpu().numpy()
+    ref = oracle.mlp_forward(_bf16(P).astype(np.float64), _bf16(X).astype(np.float64))
+    err = np.abs(got - ref) / (1.0 + np.abs(ref))
+    fwd = torch.empty((n, 9), dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(_dev(_bf16(P)), _dev(X), fwd)
+    d = np.abs(got - fwd.cpu().numpy()) / (1.0 + np.abs(ref))
+    print(f"[mlp] solver inference max scaled err {err.max():.3e}, vs forward kernel {d.max():.3e}",
+          flush=True)
+    assert err.max() < 3e-2
+    assert d.max() < 1e-2
+
+
 def test_loss_and_gradient_match_reference(lib, ctx):
     import torch
     rs = np.random.default_rng(2)
