@@ -92,9 +92,10 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--extras", default="mlp,accuracy,3d,batch",
+    ap.add_argument("--extras", default="mlp,accuracy,study,3d,batch",
                     help="other workloads to report: mlp (learned weights, trained here), "
-                         "accuracy (every form against a 2x finer FP64 run), 3d (256^3 "
+                         "accuracy (every form against a 2x finer FP64 run), study (basic "
+                         "against modified weights, 1D convergence), 3d (256^3 "
                          "shock-droplet), batch (4096 uneven tubes); empty for none")
     return ap.parse_args()
 
@@ -447,6 +448,12 @@ def main():
             other["equal_l1_1024x512"] = equal_l1(isweno, workloads, ctx, torch, fo, vals)
         except Exception as e:
             other["equal_l1_1024x512"] = {"error": repr(e)}
+    if "study" in extras:
+        try:
+            from paper_1707_00592_amd import studies
+            other["weights_study_1d"] = studies.weights_study(ctx)
+        except Exception as e:
+            other["weights_study_1d"] = {"error": repr(e)}
     if "3d" in extras:
         try:
             other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)
