@@ -30,8 +30,13 @@ MLP_NI, MLP_H, MLP_NO = 8, 32, 9
 MLP_NPARAM = MLP_H * MLP_NI + MLP_H + MLP_H * MLP_H + MLP_H + MLP_NO * MLP_H + MLP_NO
 
 
+OPCOUNT_PATH = BUILD_DIR / "libopcount.so"
+
+
 def build(verbose: bool = False) -> Path:
-    """Compile the oracle with gcc (plain C11, -O2, no fused multiply-add)."""
+    """Compile the oracle with gcc (plain C11, -O2, no fused multiply-add),
+    and its operation counter (the same source on a counting number type)
+    with g++."""
     BUILD_DIR.mkdir(exist_ok=True)
     tmp = BUILD_DIR / f"liboracle.so.tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
@@ -41,6 +46,14 @@ def build(verbose: bool = False) -> Path:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
+    tmp = BUILD_DIR / f"libopcount.so.tmp{os.getpid()}"
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
+           "-ffp-contract=off", "-Wall", "-Wno-unknown-pragmas", "-o", str(tmp),
+           str(HERE / "opcount.cpp")]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, OPCOUNT_PATH)
     return LIB_PATH
 
 
@@ -295,3 +308,89 @@ def mlp_loss_grad(params, X, Y, Cc=None):
     g = np.zeros(MLP_NPARAM)
     loss = load().or_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(Y), cp, X.shape[0], _ptr(g))
     return loss, g
+
+
+# ------------------------------------------------------ operation counts
+# Classes of opcount.cpp: additions/subtractions, multiplications,
+# divisions, square roots, comparisons.
+OP_CLASSES = ("add", "mul", "div", "sqrt", "cmp")
+_oc = None
+
+
+def load_opcount() -> C.CDLL:
+    global _oc
+    if _oc is not None:
+        return _oc
+    if not OPCOUNT_PATH.exists():
+        build()
+    lib = C.CDLL(str(OPCOUNT_PATH))
+    lp, ip = C.POINTER(C.c_long), C.POINTER(C.c_int)
+    gargs = [C.c_int, lp, _dp, ip, ip, C.c_int, C.c_int, C.c_double]
+    lib.oc_face.argtypes = [C.c_int, _dp, C.c_int, C.c_int, C.c_double, lp, ip]
+    lib.oc_piece.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_double, C.c_int, lp]
+    lib.oc_prim.argtypes = [C.c_int, _dp, C.c_int, lp]
+    lib.oc_line.argtypes = gargs + [_dp, C.c_int, C.c_long, lp, lp, lp]
+    lib.oc_eval.argtypes = gargs + [_dp, C.c_int, C.c_double, lp, lp]
+    for f in ("oc_face", "oc_piece", "oc_prim", "oc_line", "oc_eval"):
+        getattr(lib, f).restype = C.c_int
+    _oc = lib
+    return lib
+
+
+def _counts(c) -> dict:
+    return dict(zip(OP_CLASSES, (int(x) for x in c)))
+
+
+def _oc_check(code: int, what: str):
+    if code != OK:
+        raise RuntimeError(f"opcount {what}: {code}")
+
+
+def opcount_face(nt: int, q6, weights=W_MODIFIED, mood=True, eps=1e-40):
+    """Operations of one face (or_face) from its six primitive cell states;
+    returns (counts, orders used left/right)."""
+    q6 = _f64(q6).ravel(); c = (C.c_long * 5)(); o = (C.c_int * 2)()
+    _oc_check(load_opcount().oc_face(nt, _ptr(q6), int(weights), int(bool(mood)), eps, c, o),
+              "face")
+    return _counts(c), (o[0], o[1])
+
+
+def opcount_piece(kind: int, nt: int, x, weights=W_MODIFIED, eps=1e-40, order=5) -> dict:
+    """kind 0: WENO-IS value from v[5]; 1: face matrices and the projection
+    of six cells; 2: HLLC from (ql, qr); 3: positivity test of a state."""
+    x = _f64(x).ravel(); c = (C.c_long * 5)()
+    _oc_check(load_opcount().oc_piece(kind, nt, _ptr(x), int(weights), eps, order, c), "piece")
+    return _counts(c)
+
+
+def opcount_prim(ndim: int, u, d: int = 0) -> dict:
+    u = _f64(u).ravel(); c = (C.c_long * 5)()
+    _oc_check(load_opcount().oc_prim(ndim, _ptr(u), d, c), "prim")
+    return _counts(c)
+
+
+def _gargs(grid: Grid, opts: Opts):
+    return [grid.ndim, C.cast(grid.n, C.POINTER(C.c_long)), C.cast(grid.dx, _dp),
+            C.cast(grid.bc_lo, C.POINTER(C.c_int)), C.cast(grid.bc_hi, C.POINTER(C.c_int)),
+            opts.weights, opts.mood, opts.eps]
+
+
+def opcount_line(U, grid: Grid, opts: Opts, d: int, base: int = 0):
+    """One grid line of direction d through cell `base`: (total, sum of its
+    faces each counted alone, flux differences + sources + axis sum)."""
+    U = _f64(U); t = (C.c_long * 5)(); f = (C.c_long * 5)(); a = (C.c_long * 5)()
+    _oc_check(load_opcount().oc_line(*_gargs(grid, opts), _ptr(U), d, base, t, f, a), "line")
+    return _counts(t), _counts(f), _counts(a)
+
+
+def opcount_step(U, grid: Grid, opts: Opts, dt: float):
+    """One RK3 step: (total, what the three stage updates add)."""
+    U = _f64(U); c = (C.c_long * 5)(); u = (C.c_long * 5)()
+    _oc_check(load_opcount().oc_eval(*_gargs(grid, opts), _ptr(U), 1, dt, c, u), "step")
+    return _counts(c), _counts(u)
+
+
+def opcount_rhs(U, grid: Grid, opts: Opts) -> dict:
+    U = _f64(U); c = (C.c_long * 5)()
+    _oc_check(load_opcount().oc_eval(*_gargs(grid, opts), _ptr(U), 0, 0.0, c, None), "rhs")
+    return _counts(c)
