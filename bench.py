@@ -344,26 +344,36 @@ def roofline(kern, p, precision, with_traffic=False):
 
 
 def cpu_baseline(p, seconds):
-    """The oracle (plain FP64 C, OpenMP) on the same workload, first RK3
-    steps until about `seconds` of CPU work."""
+    """The oracle (plain FP64 C, OpenMP) on the same workload: the first RK3
+    steps until about `seconds` of CPU work on every host thread, then about
+    a quarter of that on one thread for a per-core figure."""
     import oracle
-    g = oracle.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
-    o = oracle.make_opts(mood=True, cfl=0.5)
-    U = p.U.copy()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        h = oracle.cfl_dt(U, g, o)
-        U, s = oracle.rk3_step(U, g, h, o)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or steps >= 200:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def sample(budget, max_steps):
+        g = oracle.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+        o = oracle.make_opts(mood=True, cfl=0.5)
+        U = p.U.copy()
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            h = oracle.cfl_dt(U, g, o)
+            U, s = oracle.rk3_step(U, g, h, o)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or steps >= max_steps:
+                return steps, el
+
+    all_threads = oracle.threads()
+    steps, el = sample(seconds, 200)
+    oracle.threads(1)
+    steps1, el1 = sample(seconds / 4, 200)
+    oracle.threads(all_threads)
     return {"value": p.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
-            "cores": cores, "kind": "oracle",
+            "cores": all_threads, "kind": "oracle",
             "sample": f"first {steps} RK3 steps of the {p.n[0]}x{p.n[1]} shock-bubble "
-                      f"({steps * 3 * p.ncells} cell-stages, {el:.1f} s)"}
+                      f"({steps * 3 * p.ncells} cell-stages, {el:.1f} s)",
+            "per_core_value": p.ncells * 3 * steps1 / el1,
+            "per_core_sample": f"first {steps1} RK3 steps on one thread ({el1:.1f} s)"}
 
 
 def rel_l1(a, b):

@@ -105,10 +105,17 @@ def load() -> C.CDLL:
     lib.or_mlp_forward.argtypes = [_dp, _dp, C.c_long, _dp]
     lib.or_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, C.c_long, _dp]
     lib.or_mlp_loss_grad.restype = C.c_double
-    for name in ("or_rhs", "or_cfl_dt", "or_rk3_step", "or_batch_step", "or_exact_star"):
+    lib.or_threads.argtypes = [C.c_int]
+    for name in ("or_rhs", "or_cfl_dt", "or_rk3_step", "or_batch_step", "or_exact_star",
+                 "or_threads"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's OpenMP loops (set when n > 0)."""
+    return int(load().or_threads(int(n)))
 
 
 def _ptr(a: np.ndarray):

@@ -13,6 +13,21 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops: set them when n > 0; returns the count in
+ * force (1 in a build without OpenMP). */
+int or_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Incremental-stencil WENO reconstruction, Sec. 3.3                          */

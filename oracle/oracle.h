@@ -95,6 +95,10 @@ void or_face(int nt, const double q6[], const or_opts *o, double ql[],
 /* Positivity test used by the MOOD cascade on a face-order state. */
 int or_pos(int nt, const double q[]);
 
+/* Threads of the oracle's OpenMP loops: sets them when n > 0 and returns
+ * the number in force (1 without OpenMP). */
+int or_threads(int n);
+
 /* ---- the semi-discrete operator and time stepping ---- */
 
 /* dU/dt = L(U), Sec. 3.1 eqs. (5)-(6), dimension by dimension. */
