@@ -99,10 +99,11 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--extras", default="mlp,accuracy,study,3d,batch",
+    ap.add_argument("--extras", default="mlp,accuracy,study,paper2d,3d,batch",
                     help="other workloads to report: mlp (learned weights, trained here), "
                          "accuracy (every form against a 2x finer FP64 run), study (basic "
-                         "against modified weights, 1D convergence), 3d (256^3 "
+                         "against modified weights, 1D convergence), paper2d (the paper's 2D "
+                         "cylinder, droplet and bubble cases at full size), 3d (256^3 "
                          "shock-droplet), batch (4096 uneven tubes); empty for none")
     return ap.parse_args()
 
@@ -150,6 +151,45 @@ def extra_3d(isweno, workloads, ctx, torch, steps=200):
     out["fp32"]["l1_rel_rho_vs_fp64"] = l1_rel(res["fp32"][0], res["fp64"][0])
     del res, U0
     torch.cuda.empty_cache()
+    return out
+
+
+def extra_paper2d(isweno, workloads, ctx, torch, steps=300):
+    """The paper's 2D workloads at the paper's finest grids: the air-R22 and
+    air-He cylinders at 3000 x 1000 between walls (MOOD off), the air-water
+    droplet at 800 x 800 (MOOD off) and the water-air bubble at 1600 x 1600
+    (MOOD on); FP64 and FP32, `steps` CFL steps each from the start."""
+    cases = [("air_R22_3000x1000", lambda: workloads.shock_gas_cylinder_2d("R22"), False),
+             ("air_He_3000x1000", lambda: workloads.shock_gas_cylinder_2d("He"), False),
+             ("air_water_droplet_800x800", lambda: workloads.air_water_2d("droplet", 800), False),
+             ("water_air_bubble_1600x1600", lambda: workloads.air_water_2d("bubble", 1600), True)]
+    out = {"steps": steps}
+    for name, make, mood in cases:
+        p = make()
+        U0 = torch.from_numpy(p.U).to("cuda")
+        r = {"cells": p.ncells, "mood": mood}
+        res = {}
+        for form, prec in (("fp64", isweno.FP64), ("fp32", isweno.FP32)):
+            U, el, st = run_steps(isweno, ctx, p, U0,
+                                  isweno.make_opts(precision=prec, mood=mood), steps, 2, torch)
+            res[form] = U
+            r[form] = {"value": p.ncells * 3 * steps / el, "status": st.status,
+                       "mood_o3": list(st.o3[:2]), "mood_o1": list(st.o1[:2])}
+        r["fp32"]["speedup_vs_fp64"] = r["fp32"]["value"] / r["fp64"]["value"]
+        r["fp32"]["l1_rel_rho_vs_fp64"] = l1_rel(res["fp32"][0], res["fp64"][0])
+        if p.bc_lo[1] == 2:
+            # symmetric about the channel axis: v odd, the rest even
+            nx, ny = p.n
+            u = res["fp64"].view(6, ny, nx)
+            m = u.flip(1).clone()
+            m[2] = -m[2]
+            scale = u.abs().amax(dim=(1, 2))
+            diff = (u - m).abs().amax(dim=(1, 2))
+            keep = scale > 0
+            r["fp64"]["mirror_asymmetry"] = float((diff[keep] / scale[keep]).max())
+        out[name] = r
+        del res, U0
+        torch.cuda.empty_cache()
     return out
 
 
@@ -471,6 +511,11 @@ def main():
             other["weights_study_1d"] = studies.weights_study(ctx)
         except Exception as e:
             other["weights_study_1d"] = {"error": repr(e)}
+    if "paper2d" in extras:
+        try:
+            other["paper_2d"] = extra_paper2d(isweno, workloads, ctx, torch)
+        except Exception as e:
+            other["paper_2d"] = {"error": repr(e)}
     if "3d" in extras:
         try:
             other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)

@@ -20,6 +20,9 @@ Problems (arXiv:1707.00592 and the workloads built on it):
     (the water/air case of Sec. 6.2 and Table 2 with the water EOS of
     Sec. 5.2)
   * 3D shock-droplet: water sphere in air hit by a Mach 2.4 air shock
+  * the paper's other workloads: the 1D shock/droplet of Sec. 5.4, the
+    air-R22 and air-He cylinders of Sec. 6.1 (Table 1) and the air-water
+    droplet and water-air bubble of Sec. 6.2 (Table 2)
   * a batch of uneven two-phase shock tubes drawn with SplitMix64
   * smooth entropy waves (the Euler analogue of the advection tests of
     Sec. 4) and random face stencils for parity checks
@@ -167,6 +170,24 @@ def shock_bubble_1d(n: int = 200) -> Problem:
                    extra={"x": x})
 
 
+def shock_droplet_1d(n: int = 200) -> Problem:
+    """Sec. 5.4 eq. (38): a Mach 2 air shock at x = 0.016 running right into
+    air at rest and a liquid layer 0.0176 < x < 0.0224 (gamma 1.932, Pinf
+    1.1645e4) on [0, 0.04], in the units of eq. (38).  The printed final
+    time 333 is read in units of 1e-6 (3.33e-4: the reflected shock is then
+    back near the left end, as eq. (37)'s 3.87 is read in units of 1e-3)."""
+    x = cell_centres(n, 0.0, 0.04)
+    rho = np.select([x < 0.016, x < 0.0176, x < 0.0224], [3.2e-3, 1.2e-3, 1.0], 1.2e-3)
+    u = np.select([x < 0.016], [44.59], 0.0)
+    p = np.select([x < 0.016], [4.5], 1.0)
+    drop = (x >= 0.0176) & (x < 0.0224)
+    ga = np.where(drop, 1.932, 1.4)
+    pi = np.where(drop, 1.1645e4, 0.0)
+    U = prim_to_cons(rho, [u], p, ga, pi)
+    return Problem(U, (n,), (0.04 / n,), (0,), (0,), t_end=3.33e-4, name="shock_droplet_1d",
+                   extra={"x": x})
+
+
 def entropy_wave(n, ndim: int = 1, amp: float = 0.2, pulse: bool = False) -> Problem:
     """Smooth density wave advected by a uniform flow (u = 1 along every
     axis, p = 1, air) on the periodic unit box: the Euler analogue of the
@@ -243,6 +264,60 @@ def shock_bubble_2d(nx: int = 1024, ny: int = 512, radius: float = 0.25,
     U = prim_to_cons(rho, [u, np.zeros_like(u)], p, ga, pi)
     return Problem(U, (nx, ny), (h, h), (0, 0), (0, 0), name="shock_bubble_2d",
                    extra={"post_shock": (rho1, u1, 1e9), "shock_speed": S, "Lx": nx * h})
+
+
+def _cylinder_problem(nx, ny, Lx, Ly, centre, radius, x_shock, pre, post, inside,
+                      bc, name, t_end):
+    """A gas or liquid cylinder in a channel, hit by a planar shock coming
+    from the right (the post-shock state fills x > x_shock).  States are
+    (rho, u, p, gamma, Pinf); sharp interface."""
+    h = Lx / nx
+    x = cell_centres(nx, 0.0, Lx)
+    y = cell_centres(ny, 0.0, Ly)
+    X, Y = np.meshgrid(x, y)                       # [j, i]
+    cyl = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 < radius ** 2
+    sh = (X > x_shock) & ~cyl
+    f = [np.where(cyl, inside[k], np.where(sh, post[k], pre[k])) for k in range(5)]
+    U = prim_to_cons(f[0], [f[1], np.zeros_like(f[1])], f[2], f[3], f[4])
+    return Problem(U, (nx, ny), (h, Ly / ny), bc[0], bc[1], t_end=t_end, name=name,
+                   extra={"pre": pre, "post": post, "inside": inside, "centre": centre,
+                          "radius": radius, "x_shock": x_shock})
+
+
+def shock_gas_cylinder_2d(gas: str = "R22", nx: int = 3000, ny: int = 1000) -> Problem:
+    """Sec. 6.1, Table 1 and its figure: a 267 mm x 89 mm channel (SI
+    units), a 50 mm cylinder of R22 (4.415, gamma 1.249) or He (0.255,
+    gamma 1.648) centred 178 mm from the left end, in air (1.4, 0, 1e5,
+    1.4) hit by the Ms = 1.22 shock whose post-shock air (1.927, -114.42,
+    1.57e5) fills the last 64 mm.  Walls (reflective) at the top and bottom,
+    transmissive ends; MOOD off in the paper.  The table's values are used
+    as printed (its post-shock velocity is about 8% above the Rankine-
+    Hugoniot value of the other entries).  t_end: the time of the paper's
+    last comparison image for each gas (190 us for R22, 245 us for He)."""
+    inside = {"R22": (4.415, 0.0, 1e5, 1.249, 0.0), "He": (0.255, 0.0, 1e5, 1.648, 0.0)}[gas]
+    return _cylinder_problem(nx, ny, 0.267, 0.089, (0.178, 0.0445), 0.025, 0.203,
+                             (1.4, 0.0, 1e5, 1.4, 0.0), (1.927, -114.42, 1.57e5, 1.4, 0.0),
+                             inside, ((0, 2), (0, 2)), f"shock_{gas}_cylinder_2d",
+                             190e-6 if gas == "R22" else 245e-6)
+
+
+def air_water_2d(case: str = "droplet", n: int = 800) -> Problem:
+    """Sec. 6.2, Table 2 and its figure: a 20 mm x 20 mm box (SI units),
+    an 8 mm cylinder centred at (12, 10) mm, hit by a shock whose
+    post-shock state fills x > 16 mm.  case "droplet": water (1000, 0, 1e5,
+    4.34, 4.84e8) in air (1.2, 0, 1e5, 1.4) hit by an Ms = 2 air shock
+    (3.2, -434, 4.56e5), MOOD off in the paper, up to 800 x 800 cells;
+    case "bubble": air (1, 0, 1e5, 1.4) in water (1000, 0, 1e5, 7, 3.31e8)
+    hit by a 1 GPa water shock (1219.9, -424.55, 1e9), MOOD on, up to
+    1600 x 1600 cells.  Non-reflecting (zero-gradient) boundaries."""
+    if case == "droplet":
+        pre, post = (1.2, 0.0, 1e5, 1.4, 0.0), (3.2, -434.0, 4.56e5, 1.4, 0.0)
+        inside = (1000.0, 0.0, 1e5, 4.34, 4.84e8)
+    else:
+        pre, post = (1000.0, 0.0, 1e5, 7.0, 3.31e8), (1219.9, -424.55, 1e9, 7.0, 3.31e8)
+        inside = (1.0, 0.0, 1e5, 1.4, 0.0)
+    return _cylinder_problem(n, n, 0.02, 0.02, (0.012, 0.010), 0.004, 0.016, pre, post,
+                             inside, ((0, 0), (0, 0)), f"air_water_{case}_2d", None)
 
 
 def shock_droplet_3d(n: int = 256, radius_cells: float = 32.0, x_shock: float = 0.3,
