@@ -282,12 +282,23 @@ enum {
   ISWENO_K_SWEEP_Y = 1,  /* stage sweep along y */
   ISWENO_K_SWEEP_Z = 2,  /* stage sweep along z */
   ISWENO_K_CFL = 3,      /* time-step reduction */
-  ISWENO_K_FUSED2D = 4,  /* fused 2D stage (x and y faces in one launch) */
   ISWENO_K_COUNT = 8
 };
 ISWENO_API int isweno_timing_enable(isweno_ctx *ctx, int enable);
 ISWENO_API int isweno_timing_read(isweno_ctx *ctx, int kind, double *total_ms,
                                   int64_t *launches);
+
+/* Field-sides per axis (counts[0..2], host memory) whose reconstruction
+ * took its shortcut since timing was last enabled.  FP64: the global
+ * indicator tau5 of eq. (25) is exactly zero, so every weight of eqs. (21)
+ * and (28) is exactly d_k and the value is the linear combination of the
+ * candidates of eq. (20) (bit-identical; no other indicator or division is
+ * formed).  FP32 form: the stencil's spread is below 1e-30 and its centre
+ * value is returned.  Counted by the stage sweeps of isweno_rhs and
+ * isweno_rk3_step while timing is enabled (never inside a captured step).
+ * Synchronises the device.  Errors: ISWENO_ERR_ARG for a null pointer,
+ * ISWENO_ERR_DEVICE. */
+ISWENO_API int isweno_shortcut_read(isweno_ctx *ctx, int64_t *counts);
 
 /* Library version string. */
 ISWENO_API const char *isweno_version(void);

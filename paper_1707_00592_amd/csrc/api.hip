@@ -17,6 +17,7 @@ struct isweno_ctx {
   double* ws = nullptr;          // two state-sized buffers (U1, U2)
   size_t ws_bytes = 0;
   unsigned long long* maxbits = nullptr;  // time-step reduction word
+  unsigned long long* shortcut = nullptr;  // 256 x 3 reconstruction-shortcut counters (timing only)
   // kernel timing
   struct Rec {
     int kind;
@@ -34,6 +35,8 @@ struct isweno_ctx {
 };
 
 namespace {
+
+constexpr size_t kShortcutBytes = 256 * 3 * sizeof(unsigned long long);
 
 hipEvent_t take_event(isweno_ctx* c) {
   if (!c->pool.empty()) {
@@ -171,6 +174,7 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
     const bool last = D == nd - 1;
     b.R = partial;
     if (!last) b.Rout = partial;
+    b.shortcut = c->timing ? c->shortcut : nullptr;  // never inside a captured graph
     KTimer t(c, ISWENO_K_SWEEP_X + D, s);
     const hipError_t e =
         isw::launch_sweep(o->precision, nd, D, b, last ? mode : isw::OUT_PARTIAL, D > 0, s);
@@ -241,7 +245,11 @@ int isweno_create(isweno_ctx** out, int device) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->ncu = prop.multiProcessorCount;
   if (hipMalloc(&c->maxbits, 256) != hipSuccess ||
-      hipMemset(c->maxbits, 0, 256) != hipSuccess) {
+      hipMemset(c->maxbits, 0, 256) != hipSuccess ||
+      hipMalloc(&c->shortcut, kShortcutBytes) != hipSuccess ||
+      hipMemset(c->shortcut, 0, kShortcutBytes) != hipSuccess) {
+    if (c->maxbits) (void)hipFree(c->maxbits);
+    if (c->shortcut) (void)hipFree(c->shortcut);
     delete c;
     return ISWENO_ERR_DEVICE;
   }
@@ -257,6 +265,7 @@ void isweno_destroy(isweno_ctx* c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->ws) (void)hipFree(c->ws);
   if (c->maxbits) (void)hipFree(c->maxbits);
+  if (c->shortcut) (void)hipFree(c->shortcut);
   drain_timing(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
@@ -361,7 +370,23 @@ int isweno_timing_enable(isweno_ctx* c, int enable) {
     c->total_ms[k] = 0.0;
     c->launches[k] = 0;
   }
+  if (hipDeviceSynchronize() != hipSuccess || hipMemset(c->shortcut, 0, kShortcutBytes) != hipSuccess)
+    return ISWENO_ERR_DEVICE;
   c->timing = enable != 0;
+  return ISWENO_OK;
+}
+
+int isweno_shortcut_read(isweno_ctx* c, int64_t* counts) {
+  if (!c || !counts) return ISWENO_ERR_ARG;
+  unsigned long long h[256 * 3];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(h, c->shortcut, kShortcutBytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return ISWENO_ERR_DEVICE;
+  for (int d = 0; d < 3; d++) {
+    unsigned long long t = 0;
+    for (int k = 0; k < 256; k++) t += h[k * 3 + d];
+    counts[d] = (int64_t)t;
+  }
   return ISWENO_OK;
 }
 

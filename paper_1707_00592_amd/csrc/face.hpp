@@ -56,6 +56,15 @@ struct Ind {
   T b1, b2, b3, b4, b12, tau;
 };
 
+// The global reference indicator tau5 of eq. (25).
+template <typename T>
+__device__ __forceinline__ T tau5(T a, T b, T c, T d, T e) {
+  const T k13 = T(ISW_K13);
+  const T t1 = e - T(2) * d + T(2) * b - a;
+  const T t2 = e - T(4) * d + T(6) * c - T(4) * b + a;
+  return T(0.25) * t1 * t1 + k13 * t2 * t2;
+}
+
 template <typename T>
 __device__ __forceinline__ Ind<T> indicators(T a, T b, T c, T d, T e) {
   const T k13 = T(ISW_K13);
@@ -72,9 +81,7 @@ __device__ __forceinline__ Ind<T> indicators(T a, T b, T c, T d, T e) {
   t1 = b - T(2) * c + d;
   t2 = b - d;
   r.b12 = k13 * t1 * t1 + T(0.25) * t2 * t2;
-  t1 = e - T(2) * d + T(2) * b - a;
-  t2 = e - T(4) * d + T(6) * c - T(4) * b + a;
-  r.tau = T(0.25) * t1 * t1 + k13 * t2 * t2;
+  r.tau = tau5<T>(a, b, c, d, e);
   return r;
 }
 
@@ -203,12 +210,41 @@ __device__ __forceinline__ double weno_f64_shared_recip(const Ind<double>& s, do
          divide(al.a4, rs) * c4;
 }
 
-// FP64 reconstruction as used by the stage kernels: the shared-reciprocal
-// form, recomputed with the plain divisions (weno_f64) on the lanes outside
-// its range (a divergent branch that a wave skips when no lane needs it).
+// Eq. (19) when the global indicator tau5 of eq. (25) is exactly zero
+// (epsilon > 0): every ratio tau5/(beta + epsilon) of eqs. (21) and (28) is
+// then exactly zero, every weight exactly d_k, and the normalisation
+// divides by the same sum on every such stencil -- the linear scheme, which
+// the indicators select on data with vanishing third and fourth
+// differences, e.g. a stencil of equal values the rounding leaves exact.
+// The candidates of eq. (20) are formed as in the general path and
+// combined in its order with d_k / sum_j d_j (divided at compile time,
+// correctly rounded as the general path divides): the same bits without
+// the divisions of the weights.
+__device__ __forceinline__ double weno_f64_linear(double a, double b, double c, double d,
+                                                  double e, bool order3) {
+  constexpr double s3 = ISW_D1 + ISW_D2;
+  constexpr double s5 = ((ISW_D1 + ISW_D2) + ISW_D3) + ISW_D4;
+  const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+  const double c2 = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+  if (order3) return (ISW_D1 / s3) * c1 + (ISW_D2 / s3) * c2;
+  const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+  const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+  return (((ISW_D1 / s5) * c1 + (ISW_D2 / s5) * c2) + (ISW_D3 / s5) * c3) +
+         (ISW_D4 / s5) * c4;
+}
+
+// FP64 reconstruction as used by the stage kernels: stencils with tau5 = 0
+// take the linear form (no other indicator is needed); the others the
+// shared-reciprocal form, recomputed with the plain divisions (weno_f64) on
+// the lanes outside its range.  The branches diverge per lane; a wave skips
+// a branch no lane needs.  nlin counts the stencils of the linear form.
 __device__ __forceinline__ double weno_f64_fast(double a, double b, double c, double d,
                                                 double e, int weights, double eps,
-                                                bool order3) {
+                                                bool order3, int& nlin) {
+  if (eps > 0.0 && tau5<double>(a, b, c, d, e) == 0.0) {
+    nlin++;
+    return weno_f64_linear(a, b, c, d, e, order3);
+  }
   const Ind<double> s = indicators<double>(a, b, c, d, e);
   double q = weno_f64_shared_recip(s, a, b, c, d, e, weights, eps, order3);
   if (!(eps >= 0x1p-200 && eps <= 0x1p100 && fast_division_range(s)))
@@ -227,10 +263,13 @@ __device__ __forceinline__ double weno_f64_fast(double a, double b, double c, do
 // the centre value: its reciprocal would overflow float.
 __device__ __forceinline__ float weno_f32(float a, float b, float c, float d,
                                           float e, int weights, float eps,
-                                          bool order3) {
+                                          bool order3, int& nshort) {
   const float s = fmaxf(fmaxf(fmaxf(fabsf(a - c), fabsf(b - c)), fabsf(d - c)),
                         fabsf(e - c));
-  if (!(s > 1e-30f)) return c;
+  if (!(s > 1e-30f)) {
+    nshort++;
+    return c;
+  }
   const float is = __builtin_amdgcn_rcpf(s);
   const float A = (a - c) * is, B = (b - c) * is, D = (d - c) * is,
               E = (e - c) * is;
@@ -263,18 +302,18 @@ __device__ __forceinline__ float weno_f32(float a, float b, float c, float d,
 
 template <typename T>
 __device__ __forceinline__ T weno(T a, T b, T c, T d, T e, int weights,
-                                  T eps, bool order3);
+                                  T eps, bool order3, int& nshort);
 template <>
 __device__ __forceinline__ double weno<double>(double a, double b, double c,
                                                double d, double e, int w,
-                                               double eps, bool o3) {
-  return weno_f64_fast(a, b, c, d, e, w, eps, o3);
+                                               double eps, bool o3, int& nshort) {
+  return weno_f64_fast(a, b, c, d, e, w, eps, o3, nshort);
 }
 template <>
 __device__ __forceinline__ float weno<float>(float a, float b, float c,
                                              float d, float e, int w,
-                                             float eps, bool o3) {
-  return weno_f32(a, b, c, d, e, w, eps, o3);
+                                             float eps, bool o3, int& nshort) {
+  return weno_f32(a, b, c, d, e, w, eps, o3, nshort);
 }
 
 // ---------------------------------------------------------------------------

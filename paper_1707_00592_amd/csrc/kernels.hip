@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   __syncthreads();
 
   // 2. faces
-  int my3 = 0, my1 = 0;
+  int my3 = 0, my1 = 0, mys = 0;
   for (int f = tid; f < TW * NF; f += NTHR) {
     const int w = D == 0 ? f / NF : f % TW;
     const int j = D == 0 ? f % NF : f / TW;
@@ -110,13 +110,14 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
     double F[NC], us;
-    int n3, n1;
-    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1);
+    int n3, n1, nf;
+    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nf);
     // the face on a tile boundary is evaluated by both tiles; count it once
     // (in the tile to its right, or the last tile for the domain's last face)
     if (j < TL || gl == geo.nL) {
       my3 += n3;
       my1 += n1;
+      mys += nf;
     }
 #pragma unroll
     for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
@@ -129,6 +130,13 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
       if (my3) atomicAdd(&g.stats->o3[D], (unsigned long long)my3);
       if (my1) atomicAdd(&g.stats->o1[D], (unsigned long long)my1);
     }
+  }
+  if (g.shortcut) {
+    // measurement only: one atomic per wave, spread over 256 slots
+    const int ws = wave_sum(mys);
+    const unsigned blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    if ((threadIdx.x & 63) == 0 && ws)
+      atomicAdd(&g.shortcut[(blk & 255) * 3 + D], (unsigned long long)ws);
   }
   __syncthreads();
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
@@ -259,8 +267,8 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
     double F[NC], us;
-    int n3, n1;
-    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, &mr);
+    int n3, n1, nf;
+    face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nf, &mr);
     if (!valid) continue;
     // the face on a tile boundary is evaluated by both tiles; count it once
     // (in the tile to its right, or the last tile for the domain's last face)

@@ -54,7 +54,15 @@ struct SweepArgs {
   double eps;
   const uint16_t* mlp; // packed bf16 network (learned weights only)
   float mlp_thr;
+  unsigned long long* shortcut;  // 256 x 3 counters of shortcut field-sides, or null
 };
+
+// Sum of an int over the 64 lanes of a wave (every lane active).
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 // Boundary map of a ghost/interior position l (-3..n+2) on a line of n
 // cells: interior index and whether the normal velocity is mirrored.
@@ -149,8 +157,9 @@ __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, 
   mlp_logits_wave(x, *mr.R, *mr.B, z);
   const float conf = 1.0f / (1.0f + __expf(-z[8]));
   if (!(conf >= mr.thr)) {
-    rl = weno<T>(w[0], w[1], w[2], w[3], w[4], W_MODIFIED, eps, false);
-    rr = weno<T>(w[5], w[4], w[3], w[2], w[1], W_MODIFIED, eps, false);
+    int nf = 0;
+    rl = weno<T>(w[0], w[1], w[2], w[3], w[4], W_MODIFIED, eps, false, nf);
+    rr = weno<T>(w[5], w[4], w[3], w[2], w[1], W_MODIFIED, eps, false, nf);
     mr.fallbacks++;
     return;
   }
@@ -182,7 +191,7 @@ __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, 
 template <typename T, int NDIM, int D, class S>
 __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int weights, T eps,
                                       T a, T b, double bd, double gd, double* ql, double* qr,
-                                      MlpRun* mr = nullptr) {
+                                      int& nshort, MlpRun* mr = nullptr) {
   constexpr int NT = NDIM - 1, NC = 5 + NT;
   constexpr int CR = 0, CU = 1 + D, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
   // Fully unrolled over the fields (static register indices for the face
@@ -228,8 +237,8 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
       double* q = side ? qr : ql;
       const double r =
           learned ? double(side ? rrm : rlm)
-          : side ? double(weno<T>(w[5], w[4], w[3], w[2], w[1], wk, eps, order3))
-                 : double(weno<T>(w[0], w[1], w[2], w[3], w[4], wk, eps, order3));
+          : side ? double(weno<T>(w[5], w[4], w[3], w[2], w[1], wk, eps, order3, nshort))
+                 : double(weno<T>(w[0], w[1], w[2], w[3], w[4], wk, eps, order3, nshort));
       if (m == 0) {
         q[0] = bd * r;
         q[1] = (-gd) * r;
@@ -253,11 +262,13 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
 
 // Full face: average state, eigen-parameters, both reconstructions, MOOD
 // cascade, HLLC.  F (face order) and us are written; o3/o1 report the
-// orders used (per side).
+// orders used (per side), nshort the field-sides of the first pass whose
+// reconstruction took its shortcut (weno<T>).
 template <typename T, int NDIM, int D, class S>
 __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
                                           double eps, double* F, double& us,
-                                          int& n3, int& n1, MlpRun* mr = nullptr) {
+                                          int& n3, int& n1, int& nshort,
+                                          MlpRun* mr = nullptr) {
   constexpr int NT = NDIM - 1, NC = 5 + NT;
   constexpr int CR = 0, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
   // L_{i+1/2}: L of eq. (11) at the mean of the two primitive states.
@@ -280,7 +291,8 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
   }
   double ql[NC], qr[NC];
   if (mr) mlp_material(Gb, Pb, mr->f6, mr->f7);
-  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, mr);
+  nshort = 0;
+  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort, mr);
   n3 = 0;
   n1 = 0;
   if (mood) {
@@ -290,7 +302,8 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
     const int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
                      (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
     if (fail) {
-      recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr);
+      int nf3 = 0;
+      recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
 #pragma unroll
       for (int side = 0; side < 2; side++) {
         if (!(fail & (1 << side))) continue;

@@ -72,13 +72,13 @@ _SIGS = {
                                   C.c_float, C.c_float, _vp]),
     "isweno_mlp_pack": (C.c_int, [_vp, _vp, _vp, _vp]),
     "isweno_timing_enable": (C.c_int, [_vp, C.c_int]),
+    "isweno_shortcut_read": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
     "isweno_timing_read": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
 }
 
-K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_CFL, K_FUSED2D = 0, 1, 2, 3, 4
-K_NAMES = {K_SWEEP_X: "sweep_x", K_SWEEP_Y: "sweep_y", K_SWEEP_Z: "sweep_z", K_CFL: "cfl",
-           K_FUSED2D: "fused2d"}
+K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_CFL = 0, 1, 2, 3
+K_NAMES = {K_SWEEP_X: "sweep_x", K_SWEEP_Y: "sweep_y", K_SWEEP_Z: "sweep_z", K_CFL: "cfl"}
 
 EXPORTED = tuple(_SIGS)
 
@@ -207,6 +207,14 @@ class Context:
     # ------------------------------------------------------------ timing
     def timing_enable(self, on: bool = True):
         check(load().isweno_timing_enable(self._h, int(bool(on))), "timing_enable")
+
+    def shortcut_read(self):
+        """Field-sides per axis whose reconstruction took its shortcut
+        (FP64: tau5 = 0, linear weights; FP32: flat stencil) since timing
+        was enabled."""
+        c = (C.c_int64 * 3)()
+        check(load().isweno_shortcut_read(self._h, c), "shortcut_read")
+        return [int(x) for x in c]
 
     def timing_read(self, kind: int):
         ms = C.c_double(0.0); n = C.c_int64(0)

@@ -150,6 +150,9 @@ def test_benchmark_constants_are_the_counted_ones():
         for d in range(nd):
             assert bench.axis_ops(nd, d) == 2 * (4 + nd) + 7 + ((4 + nd) if d else 0)
         assert bench.UPDATE_OPS_PER_STEP[nd] == 12 * (4 + nd) - 2
+    # the tau5 = 0 form: candidates 16, tau5 alone 17 (its own multiples, as
+    # in the third-order count above), combination 7, the test 1
+    assert bench.SHORTCUT_SAVING_F64 == 99 - (16 + 17 + 7 + 1)
 
 
 def test_face_constant_is_a_lower_bound_on_benchmark_states():
