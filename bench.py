@@ -31,18 +31,18 @@ import time
 # the face matrices free, a repeated operation counted once, a discarded
 # value not counted; the test suite checks these figures against it):
 #   face (smooth, subsonic, no fallback): averaged state 8, face matrices
-#   10, projection of six cells 36, (10 + nt) WENO-IS values of 99 less 35
+#   10, projection of six cells 36, (10 + nt) WENO-IS values of 101 less 25
 #   shared between the two sides, back-projection 16, positivity 6, HLLC
 #   99 + 8 nt (nt = ndim - 1 transverse velocities);
 #   cell: primitive recovery, per axis the flux difference and sources
 #   (2 nc + 7, plus nc to add the earlier axes' terms), Runge-Kutta update.
-FACE_OPS = {1: 1130, 2: 1237, 3: 1344}
+FACE_OPS = {1: 1160, 2: 1269, 3: 1378}
 # A reconstruction that takes its shortcut (FP64: tau5 of eq. (25) exactly
-# zero, so the weights are exactly d_k: candidates 16, tau5 alone 17,
-# combination 7, the test 1 = 41 of the 99 operations; FP32 form: a flat
-# stencil, its spread 8 operations) saves the difference.
-SHORTCUT_SAVING_F64 = 99 - 41
-SHORTCUT_SAVING_F32 = 99 - 8
+# zero, so the weights are exactly d_k: candidates 16, tau5 15, combination
+# 7, the test 1 = 39 of the 101 operations; FP32 form: a flat stencil, its
+# spread 8 operations) saves the difference.
+SHORTCUT_SAVING_F64 = 101 - 39
+SHORTCUT_SAVING_F32 = 101 - 8
 PRIM_OPS = {1: 7, 2: 10, 3: 13}
 UPDATE_OPS_PER_STEP = {1: 58, 2: 70, 3: 82}   # three stages per cell
 
@@ -265,8 +265,9 @@ def extra_mlp(isweno, workloads, ctx, torch, steps=300):
     for name, o in forms.items():
         U, el, kern, st, _ = run_form(isweno, ctx, p2, U2, o, steps, 5, torch, 20)
         res[name] = U
-        # face-fields evaluated over warmup, timed and kernel-timing steps
-        faces = sum(p2.ncells // p2.n[d] * (p2.n[d] + 1) for d in range(2)) * 6 * 3 * (steps + 25)
+        # learned face-fields (the four non-material fields) evaluated over
+        # both warmups, the timed and the kernel-timing steps
+        faces = sum(p2.ncells // p2.n[d] * (p2.n[d] + 1) for d in range(2)) * 4 * 3 * (steps + 30)
         out[name] = {"value": p2.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
                      "status": st.status, "kernels": kern}
         if name == "mlp":
@@ -396,6 +397,8 @@ def roofline(kern, p, precision, with_traffic=False):
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "flops_per_launch": int(flops), "avg_launch_ms": round(k["avg_ms"], 4),
             "shortcut_fraction": round(sc / (faces * 2 * (4 + nd)), 4),
+            "flops_per_launch_without_shortcuts": int(
+                flops + sc * (SHORTCUT_SAVING_F64 if precision == "f64" else SHORTCUT_SAVING_F32)),
             "published_peak_with_fma": PEAK["f64_valu_tflops"] if precision == "f64"
             else PEAK["f32_valu_tflops"],
             "hbm_at_traffic_gbs": None if traffic is None

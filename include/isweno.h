@@ -86,8 +86,12 @@ enum {
 enum {
   ISWENO_W_MODIFIED = 0, /* eq. (28), Sec. 3.3.2 (the paper's final form) */
   ISWENO_W_BASIC = 1,    /* eq. (21) with q = 1 */
-  ISWENO_W_MLP = 2       /* learned weights (isweno_mlp_*), with the
-                            eq. (28) weights as fallback */
+  ISWENO_W_MLP = 2       /* learned weights (isweno_mlp_*) for the
+                            acoustic, entropy and shear fields, with the
+                            eq. (28) weights as fallback (confidence below
+                            the threshold, or a face value outside the range
+                            of the two cells next to the face) and for the
+                            material fields Gamma, Pi throughout */
 };
 
 typedef struct {
@@ -125,8 +129,10 @@ typedef struct {
                                3rd-order reconstruction (Sec. 3.4) */
   uint64_t o1[3];           /* face sides per axis that fell back to the
                                1st-order state, eq. (32) */
-  uint64_t mlp_fallback[3]; /* ISWENO_W_MLP: face-fields per axis whose
-                               learned weights were replaced */
+  uint64_t mlp_fallback[3]; /* ISWENO_W_MLP: per axis, face-fields below
+                               the confidence threshold plus face sides
+                               outside their cell range, whose learned
+                               weights were replaced */
   int32_t status;           /* ISWENO_OK, or ISWENO_ERR_NONPHYSICAL once an
                                input cell of any evaluation had rho <= 0,
                                Gamma <= 0, c^2 <= 0 or a non-finite value;
@@ -272,9 +278,10 @@ ISWENO_API int isweno_mlp_pack(isweno_ctx *ctx, const float *params, uint16_t *p
                     void *stream);
 
 /* ---- kernel timing (measurement support) ----
- * While enabled, every kernel the library launches outside a graph is
- * bracketed by HIP events recorded on its launch stream; durations are
- * accumulated per kernel kind.  isweno_timing_read synchronises on the
+ * While enabled, every stage and time-step launch the library makes outside
+ * a graph records a pair of HIP events through the dispatch itself (start
+ * and end of its kernels, on its launch stream, without the launch latency
+ * around them); durations are accumulated per kernel kind.  isweno_timing_read synchronises on the
  * recorded events and returns the total milliseconds and launch count of
  * one kind since the last enable. */
 enum {

@@ -50,7 +50,12 @@ void or_weno_candidates(const double v[5], double cand[4]) {
 /* Smoothness indicators beta_1..beta_4 (eq. (24)), beta_12 of the central
  * 3-point stencil {i-1,i,i+1} (Sec. 3.3.2; its printed stencil name
  * "{i-1,i,i+2}" disagrees with its formula, the formula is used) and the
- * global reference indicator tau_5 (eq. (25)). */
+ * global reference indicator tau_5 (eq. (25)).  Eq. (25) fixes tau_5's value,
+ * not an order of its sums; its two bracketed sums are formed with the
+ * stencil's mirror-image points paired, (e - a) - 2 (d - b) and
+ * ((e + a) - 4 (d + b)) + 6 c, which keeps tau_5 exactly zero on a stencil
+ * of equal values (as the exact formula is) and identical for a stencil and
+ * its mirror image. */
 void or_weno_indicators(const double v[5], double ind[6]) {
   const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4];
   const double k13 = 13.0 / 12.0;
@@ -66,8 +71,8 @@ void or_weno_indicators(const double v[5], double ind[6]) {
   t1 = b - 2.0 * c + d;
   t2 = b - d;
   ind[4] = k13 * t1 * t1 + 0.25 * t2 * t2;
-  t1 = e - 2.0 * d + 2.0 * b - a;
-  t2 = e - 4.0 * d + 6.0 * c - 4.0 * b + a;
+  t1 = (e - a) - 2.0 * (d - b);
+  t2 = ((e + a) - 4.0 * (d + b)) + 6.0 * c;
   ind[5] = 0.25 * t1 * t1 + k13 * t2 * t2;
 }
 

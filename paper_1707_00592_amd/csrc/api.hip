@@ -49,27 +49,25 @@ hipEvent_t take_event(isweno_ctx* c) {
   return e;
 }
 
-// Brackets one launch with events when timing is enabled.
+// Timing of one launch when enabled: a pair of events the launch itself
+// records at the start and end of its kernels (on the launch stream),
+// collected into the context's records after the launch.
 struct KTimer {
   isweno_ctx* c;
   int kind;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  KTimer(isweno_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+  isw::LaunchEvents ev;
+  KTimer(isweno_ctx* c_, int kind_) : c(c_), kind(kind_) {
     if (c && c->timing) {
-      a = take_event(c);
-      if (a && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+      ev.start = take_event(c);
+      ev.stop = ev.start ? take_event(c) : nullptr;
+      if (!ev.stop && ev.start) {
+        c->pool.push_back(ev.start);
+        ev.start = nullptr;
+      }
     }
   }
   ~KTimer() {
-    if (!a) return;
-    hipEvent_t b = take_event(c);
-    if (b && hipEventRecord(b, s) == hipSuccess) {
-      c->recs.push_back({kind, a, b});
-    } else {
-      c->pool.push_back(a);
-      if (b) c->pool.push_back(b);
-    }
+    if (ev.start) c->recs.push_back({kind, ev.start, ev.stop});
   }
 };
 
@@ -175,9 +173,9 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
     b.R = partial;
     if (!last) b.Rout = partial;
     b.shortcut = c->timing ? c->shortcut : nullptr;  // never inside a captured graph
-    KTimer t(c, ISWENO_K_SWEEP_X + D, s);
-    const hipError_t e =
-        isw::launch_sweep(o->precision, nd, D, b, last ? mode : isw::OUT_PARTIAL, D > 0, s);
+    KTimer t(c, ISWENO_K_SWEEP_X + D);
+    const hipError_t e = isw::launch_sweep(o->precision, nd, D, b,
+                                           last ? mode : isw::OUT_PARTIAL, D > 0, s, t.ev);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -192,9 +190,9 @@ hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o
   double* U2 = c->ws + sz;
   hipError_t e;
   if (o->cfl > 0.0) {
-    KTimer t(c, ISWENO_K_CFL, s);
+    KTimer t(c, ISWENO_K_CFL);
     if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt,
-                             c->ncu, s)) != hipSuccess)
+                             c->ncu, s, t.ev)) != hipSuccess)
       return e;
   }
   isw::SweepArgs a = base_args(g, o, stats);
@@ -296,9 +294,9 @@ int isweno_cfl_dt(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, con
   if (!o || !(o->cfl > 0.0)) return ISWENO_ERR_ARG;
   if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  KTimer t(c, ISWENO_K_CFL, s);
+  KTimer t(c, ISWENO_K_CFL);
   return isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt, c->ncu,
-                         s) == hipSuccess
+                         s, t.ev) == hipSuccess
              ? ISWENO_OK
              : ISWENO_ERR_DEVICE;
 }

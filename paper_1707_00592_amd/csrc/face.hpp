@@ -33,9 +33,24 @@ __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
 
 // c^2 = gamma (p + Pinf) / rho of the stiffened gas (eq. (2)) in terms of
 // Gamma = 1/(gamma-1) and Pi = gamma Pinf/(gamma-1).
+// Quotient in the arithmetic of T: the IEEE division for double (the FP64
+// path reproduces the oracle's rounding); for the float form, x times the
+// hardware reciprocal (within about 1 ulp), whose results are bounded, not
+// exact.  Zero and infinite divisors give the same infinities and NaNs.
+template <typename T>
+__device__ __forceinline__ T qdiv(T x, T y);
+template <>
+__device__ __forceinline__ double qdiv<double>(double x, double y) {
+  return x / y;
+}
+template <>
+__device__ __forceinline__ float qdiv<float>(float x, float y) {
+  return x * __builtin_amdgcn_rcpf(y);
+}
+
 template <typename T>
 __device__ __forceinline__ T sound2(T rho, T p, T G, T P) {
-  return ((G + T(1)) * p + P) / (G * rho);
+  return qdiv<T>((G + T(1)) * p + P, G * rho);
 }
 
 // Admissibility used by the MOOD cascade: rho > 0, Gamma > 0 and
@@ -56,12 +71,14 @@ struct Ind {
   T b1, b2, b3, b4, b12, tau;
 };
 
-// The global reference indicator tau5 of eq. (25).
+// The global reference indicator tau5 of eq. (25), its bracketed sums
+// formed with the mirror-image points paired: exactly zero on a stencil of
+// equal values and the same for a stencil and its mirror image.
 template <typename T>
 __device__ __forceinline__ T tau5(T a, T b, T c, T d, T e) {
   const T k13 = T(ISW_K13);
-  const T t1 = e - T(2) * d + T(2) * b - a;
-  const T t2 = e - T(4) * d + T(6) * c - T(4) * b + a;
+  const T t1 = (e - a) - T(2) * (d - b);
+  const T t2 = ((e + a) - T(4) * (d + b)) + T(6) * c;
   return T(0.25) * t1 * t1 + k13 * t2 * t2;
 }
 
@@ -215,7 +232,7 @@ __device__ __forceinline__ double weno_f64_shared_recip(const Ind<double>& s, do
 // then exactly zero, every weight exactly d_k, and the normalisation
 // divides by the same sum on every such stencil -- the linear scheme, which
 // the indicators select on data with vanishing third and fourth
-// differences, e.g. a stencil of equal values the rounding leaves exact.
+// differences -- every stencil of equal values, among others.
 // The candidates of eq. (20) are formed as in the general path and
 // combined in its order with d_k / sum_j d_j (divided at compile time,
 // correctly rounded as the general path divides): the same bits without
@@ -368,9 +385,9 @@ __device__ __forceinline__ void star_flux(const T* q, T Sk, T Ss, T* F,
 #pragma unroll
   for (int k = 0; k < NC; k++) {
     const T Dk = (k == 1) ? T(1) : ((k == 2 + NT) ? Ss : T(0));
-    F[k] = (Ss * (Sk * Uk[k] - Fk[k]) + sp * Dk) / den;
+    F[k] = qdiv<T>(Ss * (Sk * Uk[k] - Fk[k]) + sp * Dk, den);
   }
-  us = Ss * (Sk - un) / den;
+  us = qdiv<T>(Ss * (Sk - un), den);
 }
 
 template <typename T, int NT>
@@ -382,15 +399,15 @@ __device__ __forceinline__ void hllc(const T* ql, const T* qr, T* F, T& us) {
   const T cr2 = sound2<T>(rr, pr, qr[3 + NT], qr[4 + NT]);
   const T cl = sqrt(cl2), cr = sqrt(cr2);
   const T sl = sqrt(rl), sr = sqrt(rr);
-  const T ubar = (sl * ul + sr * ur) / (sl + sr);
-  const T cbar2 = (sl * cl2 + sr * cr2) / (sl + sr) +
-                  T(0.5) * sl * sr / ((sl + sr) * (sl + sr)) * (ur - ul) *
+  const T ubar = qdiv<T>(sl * ul + sr * ur, sl + sr);
+  const T cbar2 = qdiv<T>(sl * cl2 + sr * cr2, sl + sr) +
+                  qdiv<T>(T(0.5) * sl * sr, (sl + sr) * (sl + sr)) * (ur - ul) *
                       (ur - ul);
   const T cbar = sqrt(cbar2);
   const T Sl = dmin<T>(dmin<T>(ubar - cbar, ul - cl), T(0));
   const T Sr = dmax<T>(dmax<T>(ubar + cbar, ur + cr), T(0));
-  const T Ss = (pr - pl + rl * ul * (Sl - ul) - rr * ur * (Sr - ur)) /
-               (rl * (Sl - ul) - rr * (Sr - ur));
+  const T Ss = qdiv<T>(pr - pl + rl * ul * (Sl - ul) - rr * ur * (Sr - ur),
+                      rl * (Sl - ul) - rr * (Sr - ur));
   if (Ss != T(0)) {
     const bool left = Ss > T(0);
     T qs[NC];

@@ -1,4 +1,5 @@
 // Stage kernels and time-step reduction of the WENO-IS operator for gfx950.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -403,7 +404,7 @@ struct TileShape<NDIM, 2> {
 };
 
 template <typename T, int NDIM, int D, int MODE, bool READ_R, bool LEARNED>
-static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s) {
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   using TS = TileShape<NDIM, D>;
   constexpr int NTHR = 256;
   const int64_t nL = a.n[D];
@@ -414,63 +415,76 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s) {
   const int64_t blocks = ((nL + TS::TL - 1) / TS::TL) * ((nA + TS::TW - 1) / TS::TW) * nT;
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if constexpr (LEARNED)
-    hipLaunchKernelGGL((sweep_mlp_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
-                       dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
-  else
-    hipLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
-                       dim3((unsigned)blocks), dim3(NTHR), 0, s, a);
+  // with events (timing only, never captured), the dispatch records its own
+  // start and end: the kernel's duration without the launch latency
+  const dim3 grid((unsigned)blocks), block(NTHR);
+  if constexpr (LEARNED) {
+    if (ev.start)
+      hipExtLaunchKernelGGL((sweep_mlp_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                            grid, block, 0, s, ev.start, ev.stop, 0, a);
+    else
+      hipLaunchKernelGGL((sweep_mlp_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                         grid, block, 0, s, a);
+  } else {
+    if (ev.start)
+      hipExtLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                            grid, block, 0, s, ev.start, ev.stop, 0, a);
+    else
+      hipLaunchKernelGGL((sweep_kernel<T, NDIM, D, TS::TL, TS::TW, NTHR, MODE, READ_R>),
+                         grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int NDIM, int D, bool LEARNED>
-static hipError_t launch_sweep_d(const SweepArgs& a, int mode, bool readR, hipStream_t s) {
+static hipError_t launch_sweep_d(const SweepArgs& a, int mode, bool readR, hipStream_t s,
+                                 LaunchEvents ev) {
   switch (mode) {
     case OUT_PARTIAL:
-      return readR ? launch_sweep_t<T, NDIM, D, OUT_PARTIAL, true, LEARNED>(a, s)
-                   : launch_sweep_t<T, NDIM, D, OUT_PARTIAL, false, LEARNED>(a, s);
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_PARTIAL, true, LEARNED>(a, s, ev)
+                   : launch_sweep_t<T, NDIM, D, OUT_PARTIAL, false, LEARNED>(a, s, ev);
     case OUT_RHS:
-      return readR ? launch_sweep_t<T, NDIM, D, OUT_RHS, true, LEARNED>(a, s)
-                   : launch_sweep_t<T, NDIM, D, OUT_RHS, false, LEARNED>(a, s);
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RHS, true, LEARNED>(a, s, ev)
+                   : launch_sweep_t<T, NDIM, D, OUT_RHS, false, LEARNED>(a, s, ev);
     case OUT_RK1:
-      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK1, true, LEARNED>(a, s)
-                   : launch_sweep_t<T, NDIM, D, OUT_RK1, false, LEARNED>(a, s);
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK1, true, LEARNED>(a, s, ev)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK1, false, LEARNED>(a, s, ev);
     case OUT_RK2:
-      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK2, true, LEARNED>(a, s)
-                   : launch_sweep_t<T, NDIM, D, OUT_RK2, false, LEARNED>(a, s);
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK2, true, LEARNED>(a, s, ev)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK2, false, LEARNED>(a, s, ev);
     default:
-      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK3, true, LEARNED>(a, s)
-                   : launch_sweep_t<T, NDIM, D, OUT_RK3, false, LEARNED>(a, s);
+      return readR ? launch_sweep_t<T, NDIM, D, OUT_RK3, true, LEARNED>(a, s, ev)
+                   : launch_sweep_t<T, NDIM, D, OUT_RK3, false, LEARNED>(a, s, ev);
   }
 }
 
 template <typename T, bool LEARNED>
 static hipError_t launch_sweep_p(int ndim, int D, const SweepArgs& a, int mode, bool readR,
-                                 hipStream_t s) {
-  if (ndim == 1) return launch_sweep_d<T, 1, 0, LEARNED>(a, mode, readR, s);
+                                 hipStream_t s, LaunchEvents ev) {
+  if (ndim == 1) return launch_sweep_d<T, 1, 0, LEARNED>(a, mode, readR, s, ev);
   if (ndim == 2) {
-    return D == 0 ? launch_sweep_d<T, 2, 0, LEARNED>(a, mode, readR, s)
-                  : launch_sweep_d<T, 2, 1, LEARNED>(a, mode, readR, s);
+    return D == 0 ? launch_sweep_d<T, 2, 0, LEARNED>(a, mode, readR, s, ev)
+                  : launch_sweep_d<T, 2, 1, LEARNED>(a, mode, readR, s, ev);
   }
-  if (D == 0) return launch_sweep_d<T, 3, 0, LEARNED>(a, mode, readR, s);
-  if (D == 1) return launch_sweep_d<T, 3, 1, LEARNED>(a, mode, readR, s);
-  return launch_sweep_d<T, 3, 2, LEARNED>(a, mode, readR, s);
+  if (D == 0) return launch_sweep_d<T, 3, 0, LEARNED>(a, mode, readR, s, ev);
+  if (D == 1) return launch_sweep_d<T, 3, 1, LEARNED>(a, mode, readR, s, ev);
+  return launch_sweep_d<T, 3, 2, LEARNED>(a, mode, readR, s, ev);
 }
 
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
-                        bool readR, hipStream_t s) {
+                        bool readR, hipStream_t s, LaunchEvents ev) {
   if (a.weights == W_MLP) {
     // learned weights: float32 reconstruction with a packed network only
     if (precision != 1 || !a.mlp) return hipErrorInvalidValue;
-    return launch_sweep_p<float, true>(ndim, D, a, mode, readR, s);
+    return launch_sweep_p<float, true>(ndim, D, a, mode, readR, s, ev);
   }
-  return precision == 1 ? launch_sweep_p<float, false>(ndim, D, a, mode, readR, s)
-                        : launch_sweep_p<double, false>(ndim, D, a, mode, readR, s);
+  return precision == 1 ? launch_sweep_p<float, false>(ndim, D, a, mode, readR, s, ev)
+                        : launch_sweep_p<double, false>(ndim, D, a, mode, readR, s, ev);
 }
 
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
-                      int ncu, hipStream_t s) {
+                      int ncu, hipStream_t s, LaunchEvents ev) {
   const int64_t N = n[0] * n[1] * n[2];
   int64_t blocks = (N + 1023) / 1024;
   // one workgroup per CU: every workgroup ends in one atomic on the same
@@ -479,18 +493,30 @@ hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double*
   const int64_t cap = (int64_t)ncu;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
+  // events (timing only, never captured): start of the reduction, end of
+  // the finalisation
+  const dim3 grid((unsigned)blocks), block(256);
+  auto reduce = [&](auto kern) {
+    if (ev.start)
+      hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev.start, nullptr, 0, U, n[0], n[1], n[2],
+                            dx[0], dx[1], dx[2], maxbits);
+    else
+      hipLaunchKernelGGL(kern, grid, block, 0, s, U, n[0], n[1], n[2], dx[0], dx[1], dx[2],
+                         maxbits);
+  };
   if (ndim == 1)
-    hipLaunchKernelGGL(cfl_reduce_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
+    reduce(cfl_reduce_kernel<1>);
   else if (ndim == 2)
-    hipLaunchKernelGGL(cfl_reduce_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
+    reduce(cfl_reduce_kernel<2>);
   else
-    hipLaunchKernelGGL(cfl_reduce_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, n[0],
-                       n[1], n[2], dx[0], dx[1], dx[2], maxbits);
+    reduce(cfl_reduce_kernel<3>);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, maxbits, cfl, dt_max, dt);
+  if (ev.stop)
+    hipExtLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, nullptr, ev.stop, 0,
+                          maxbits, cfl, dt_max, dt);
+  else
+    hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, maxbits, cfl, dt_max, dt);
   return hipGetLastError();
 }
 

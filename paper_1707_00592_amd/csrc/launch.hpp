@@ -9,15 +9,21 @@ namespace isw {
 struct SweepArgs;
 struct BatchArgs;
 
+// Optional timing events: when set, the launch itself records the start of
+// its (first) kernel into start and the end of its (last) kernel into stop.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // One axis D of a stage: mode is an OutMode, readR adds the partial sum of
 // the previous axes.  precision: 0 = FP64, 1 = FP32 reconstruction/flux.
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
-                        bool readR, hipStream_t s);
+                        bool readR, hipStream_t s, LaunchEvents ev = {});
 
 // dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); maxbits is
 // a zeroed device word, left zeroed on exit.
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
-                      int ncu, hipStream_t s);
+                      int ncu, hipStream_t s, LaunchEvents ev = {});
 
 }  // namespace isw

@@ -148,10 +148,24 @@ __device__ __host__ constexpr int axis_comp(int k) {
 // order) at stencil position j.
 // Learned weights for one field: the network on the 64 faces of the wave
 // (two 32-sample tiles, all lanes take part), its weights applied to the
-// candidates of eq. (20) as in eq. (19); below the confidence threshold the
-// eq. (28) weights are used instead.
+// candidates of eq. (20) as in eq. (19); below the confidence threshold, or
+// for a side whose value leaves the range of the two cells next to the
+// face, the eq. (28) weights are used instead (each counted as a fallback).
 template <typename T>
 __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, T& rr) {
+  // Flat on both sides (spread below 1e-30, as the plain float form tests
+  // it): every candidate is the centre value, so both the learned weights
+  // and their fallback give it exactly.  A wave whose every lane is flat
+  // skips the network (which needs the whole wave).
+  const T sl = fmaxf(fmaxf(fmaxf(fabsf(w[0] - w[2]), fabsf(w[1] - w[2])), fabsf(w[3] - w[2])),
+                     fabsf(w[4] - w[2]));
+  const T sr = fmaxf(fmaxf(fmaxf(fabsf(w[5] - w[3]), fabsf(w[4] - w[3])), fabsf(w[2] - w[3])),
+                     fabsf(w[1] - w[3]));
+  if (__all(!(sl > T(1e-30)) && !(sr > T(1e-30)))) {
+    rl = w[2];
+    rr = w[3];
+    return;
+  }
   float x[8], z[9];
   mlp_features<T>(w, mr.f6, mr.f7, x);
   mlp_logits_wave(x, *mr.R, *mr.B, z);
@@ -184,7 +198,19 @@ __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, 
     const float d4 = (1.0f / 3.0f) * (A - C) - (7.0f / 6.0f) * (B - C);
     const float q =
         C + (e[0] * d1 + e[1] * d2 + e[2] * d3 + e[3] * d4) * __builtin_amdgcn_rcpf(sum);
-    if (side) rr = T(q); else rl = T(q);
+    // A face value outside the range of the two cells next to the face (a
+    // confident but wrong prediction: an overshoot, or a material property
+    // mixed into a pure fluid) takes the eq. (28) weights instead.
+    if (q >= fminf(C, D_) && q <= fmaxf(C, D_)) {
+      if (side) rr = T(q); else rl = T(q);
+    } else {
+      int nf = 0;
+      if (side)
+        rr = weno<T>(w[5], w[4], w[3], w[2], w[1], W_MODIFIED, eps, false, nf);
+      else
+        rl = weno<T>(w[0], w[1], w[2], w[3], w[4], W_MODIFIED, eps, false, nf);
+      mr.fallbacks++;
+    }
   }
 }
 
@@ -227,7 +253,9 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
       }
     }
     T rlm = T(0), rrm = T(0);
-    const bool learned = mr != nullptr && !order3;
+    // the material fields (Gamma, Pi) keep the eq. (28) weights: their
+    // reconstruction decides the mixture at an interface
+    const bool learned = mr != nullptr && !order3 && m != 2 + NT && m != 3 + NT;
     if (learned) mlp_field<T>(w, *mr, eps, rlm, rrm);
     const int wk = weights == W_MLP ? W_MODIFIED : weights;
 #pragma unroll
@@ -282,7 +310,7 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
     const T c2 = sound2<T>(T(rb), T(pb), T(Gb), T(Pb));
     const T c = sqrt(c2);
     a = T(rb) * c / T(2);
-    b = T(1) / c2;
+    b = qdiv<T>(T(1), c2);
     bd = double(b);
     gd = 1.0 / double(T(rb) * c);
     if (sizeof(T) == 8) {

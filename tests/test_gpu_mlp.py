@@ -200,14 +200,17 @@ def test_training_and_learned_weights_in_the_solver(lib, ctx):
     """Train on faces from plain runs (gas-liquid shock tube and a small
     shock-droplet), then run the shock tube with the learned weights: the
     loss drops, the run stays physical, and its error against the exact
-    solution is reported next to the plain FP32 path's."""
+    solution is reported next to the plain FP32 path's.  Both runs use the
+    MOOD cascade, the learned form's safety net behind its confidence
+    fallback (without it a learned reconstruction at the water-air
+    interface can turn a cell non-physical)."""
     import torch
     from paper_1707_00592_amd import learned
     opts64 = lib.make_opts()
     X, Y = learned.collect(ctx, [wl.sod_gas_liquid(200), wl.shock_droplet_3d(24, 3.0)],
                            opts64, steps=20, every=5, stride=3, max_rows=200000)
     Xs, Ys = learned.stratify(X, Y)
-    P, hist = learned.train(ctx, Xs, Ys, steps=400, batch=8192, lr=3e-3, log_every=100)
+    P, hist = learned.train(ctx, Xs, Ys, steps=1500, batch=16384, lr=3e-3, log_every=500)
     print(f"[mlp] samples {Xs.shape[0]} loss history {hist}", flush=True)
     assert hist[-1][1] < 0.8 * hist[0][1]
     ev = learned.evaluate(ctx, P, Xs, Ys)
@@ -217,13 +220,15 @@ def test_training_and_learned_weights_in_the_solver(lib, ctx):
     p = wl.sod_gas_liquid(200)
     g = lib.make_grid(p.n, p.dx, 0, 0)
     res = {}
-    for name, o in (("fp32", lib.make_opts(precision=lib.FP32, mood=False)),
-                    ("mlp", lib.make_opts(precision=lib.FP32, weights=lib.W_MLP, mood=False,
+    for name, o in (("fp32", lib.make_opts(precision=lib.FP32, mood=True)),
+                    ("mlp", lib.make_opts(precision=lib.FP32, weights=lib.W_MLP, mood=True,
                                           mlp_params=packed))):
         U = _dev(p.U)
         st = lib.new_stats()
         lib.Solver(g, o, ctx).run(U, t_end=p.t_end, stats=st)
         s = lib.read_stats(st)
+        print(f"[mlp] shock tube {name}: status {s.status} mood o3 {s.o3[0]} o1 {s.o1[0]} "
+              f"fallbacks {s.mlp_fallback[0]}", flush=True)
         assert s.status == 0
         W = oracle.exact_sample(p.extra["WL"], p.extra["WR"], (p.extra["x"] - 0.7) / p.t_end)
         res[name] = (np.abs(U.cpu().numpy()[0] - W[:, 0]).mean() / 1000.0, s.mlp_fallback[0])

@@ -303,3 +303,65 @@ def test_graph_replays_match_direct_launches(lib, ctx):
             assert dt.item() == direct[k][1], (rep, k)
             assert np.array_equal(got, direct[k][0]), (rep, k)
     print("[parity] graph replays: bitwise=True over 2 x 4 steps", flush=True)
+
+
+def _host_shortcut_count(U, n, axis):
+    """Field-sides of one axis whose tau5 (eq. (25)) is exactly zero, formed
+    with the kernel's formulas and operation order (zero-gradient ghosts)."""
+    nx, ny = n
+    r = U[0]
+    u = U[1] / r
+    v = U[2] / r
+    ke = u * u + v * v
+    p = (U[3] - 0.5 * r * ke - U[5]) / U[4]
+    q = np.stack([r, u, v, p, U[4], U[5]]).reshape(6, ny, nx)
+    ax = 2 - axis
+    pad = [(0, 0)] * 3
+    pad[ax] = (3, 3)
+    e = np.pad(q, pad, mode="edge")
+    m = q.shape[ax]
+    W = []
+    for k in range(6):
+        sl = [slice(None)] * 3
+        sl[ax] = slice(k, k + m + 1)
+        W.append(e[tuple(sl)])
+    un, ut = 1 + axis, 2 - axis
+    rb = 0.5 * (W[2][0] + W[3][0])
+    pb = 0.5 * (W[2][3] + W[3][3])
+    Gb = 0.5 * (W[2][4] + W[3][4])
+    Pb = 0.5 * (W[2][5] + W[3][5])
+    c2 = ((Gb + 1.0) * pb + Pb) / (Gb * rb)
+    c = np.sqrt(c2)
+    a = rb * c / 2.0
+    b = 1.0 / c2
+    fields = [[(-a) * w[un] + 0.5 * w[3] for w in W], [w[0] - b * w[3] for w in W],
+              [w[ut] for w in W], [w[4] for w in W], [w[5] for w in W],
+              [a * w[un] + 0.5 * w[3] for w in W]]
+
+    def tau_zero(A, B, C_, D, E):
+        t1 = (E - A) - 2.0 * (D - B)
+        t2 = ((E + A) - 4.0 * (D + B)) + 6.0 * C_
+        return (0.25 * t1 * t1 + (13.0 / 12.0) * t2 * t2) == 0.0
+
+    total = 0
+    for f in fields:
+        total += int(tau_zero(f[0], f[1], f[2], f[3], f[4]).sum())
+        total += int(tau_zero(f[5], f[4], f[3], f[2], f[1]).sum())
+    return total
+
+
+def test_linear_weight_shortcut_is_counted_and_exact(lib, ctx):
+    """FP64 reconstructions whose tau5 is exactly zero take the
+    linear-weight form: the evaluation stays bit-for-bit with the oracle,
+    and the kernel's count of such field-sides equals a host count."""
+    p = wl.shock_bubble_2d(128, 64)
+    og, ig = _grids(p)
+    ref, _ = oracle.rhs(p.U, og, oracle.make_opts())
+    ctx.timing_enable(True)
+    got = ctx.rhs(_dev(p.U), ig, lib.make_opts()).cpu().numpy()
+    counts = ctx.shortcut_read()
+    ctx.timing_enable(False)
+    _check(got, ref, what="rhs with the shortcut counted")
+    host = [_host_shortcut_count(p.U, p.n, d) for d in (0, 1)]
+    print(f"[parity] shortcut field-sides {counts[:2]} host {host}", flush=True)
+    assert counts[:2] == host and min(host) > 0

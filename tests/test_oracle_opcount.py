@@ -36,19 +36,20 @@ def test_weno_is_counts():
     """Eqs. (19)-(28) on one stencil.
     Candidates (eq. (20)): 2+1, 2+1, 3+2, 3+2 -> 16.
     Indicators: beta1, beta2 2 each; beta3 12; beta4 11 (3c already made
-    for beta3); beta12 9; tau5 13 (2d, 2b, 4d, 4b shared) -> 49.
+    for beta3); beta12 9; tau5 15 (e-a, d-b, e+a, d+b, 2(d-b), 4(d+b), 6c
+    and the two differences: 10, the squares 5) -> 51.
     Modified weights (eq. (28)): tau5/(beta12+eps) 2, alpha1,2 5 each,
     alpha3,4 4 each, sum 3, normalisation 4 -> 27.  Combination 4+3 = 7.
     Basic weights (eq. (21)): beta12 unused (-9), alpha 4 x 4, sum 3,
-    normalisation 4.  Third order: only the 2-point stencils; tau5 pays
-    for its own multiples (17), beta1, beta2, beta12, and 2 normalisations."""
+    normalisation 4.  Third order: only the 2-point stencils; beta1,
+    beta2, beta12, tau5, and 2 normalisations."""
     v = np.random.default_rng(1).random(5)
     m = oracle.opcount_piece(0, 1, v)
-    assert (tot(m), m["div"], m["sqrt"], m["cmp"]) == (16 + 49 + 27 + 7, 9, 0, 0)
+    assert (tot(m), m["div"], m["sqrt"], m["cmp"]) == (16 + 51 + 27 + 7, 9, 0, 0)
     b = oracle.opcount_piece(0, 1, v, weights=oracle.W_BASIC)
-    assert tot(b) == 16 + (49 - 9) + (16 + 3 + 4) + 7 and b["div"] == 8
+    assert tot(b) == 16 + (51 - 9) + (16 + 3 + 4) + 7 and b["div"] == 8
     o3 = oracle.opcount_piece(0, 1, v, order=3)
-    assert tot(o3) == 6 + (2 + 2 + 9 + 17) + (2 + 5 + 5 + 1 + 2) + 3
+    assert tot(o3) == 6 + (2 + 2 + 9 + 15) + (2 + 5 + 5 + 1 + 2) + 3
 
 
 @pytest.mark.parametrize("ndim", [1, 2, 3])
@@ -104,13 +105,13 @@ def test_hllc_count(nt):
 
 def face_by_hand(nt):
     """Averaged state 8, face matrices 10 (R needed now), projection 36,
-    (10 + nt) live reconstructions of 99 (the right transverse velocities
-    feed only the unused right flux), less 7 operations shared by the left
+    (10 + nt) live reconstructions of 101 (the right transverse velocities
+    feed only the unused right flux), less 5 operations shared by the left
     and right reconstruction of each of the five fields both sides use
-    (q_i/2, q_{i+1}/2 and their sum, 2 q_i, 2 q_{i+1}, q_{i-1} - 2 q_i,
-    q_{i+2} - 2 q_{i+1}), back-projection 2 x 8, positivity 2 x 3
-    comparisons (the rest is shared with the sound speeds), HLLC."""
-    return 8 + 10 + 36 + (10 + nt) * 99 - 5 * 7 + 16 + 6 + (99 + 8 * nt)
+    (q_i/2, q_{i+1}/2 and their sum, 2 q_i, 2 q_{i+1}), back-projection
+    2 x 8, positivity 2 x 3 comparisons (the rest is shared with the sound
+    speeds), HLLC."""
+    return 8 + 10 + 36 + (10 + nt) * 101 - 5 * 5 + 16 + 6 + (99 + 8 * nt)
 
 
 @pytest.mark.parametrize("nt", [0, 1, 2])
@@ -150,9 +151,10 @@ def test_benchmark_constants_are_the_counted_ones():
         for d in range(nd):
             assert bench.axis_ops(nd, d) == 2 * (4 + nd) + 7 + ((4 + nd) if d else 0)
         assert bench.UPDATE_OPS_PER_STEP[nd] == 12 * (4 + nd) - 2
-    # the tau5 = 0 form: candidates 16, tau5 alone 17 (its own multiples, as
-    # in the third-order count above), combination 7, the test 1
-    assert bench.SHORTCUT_SAVING_F64 == 99 - (16 + 17 + 7 + 1)
+    # the tau5 = 0 form: candidates 16, tau5 15, combination 7, the test 1
+    assert bench.SHORTCUT_SAVING_F64 == 101 - (16 + 15 + 7 + 1)
+    # the FP32 flat return: four differences, three maxima, the test
+    assert bench.SHORTCUT_SAVING_F32 == 101 - 8
 
 
 def test_face_constant_is_a_lower_bound_on_benchmark_states():

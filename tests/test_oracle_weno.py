@@ -174,6 +174,31 @@ def test_tau5_leading_terms_match_taylor_expansion():
                                                                rel=1e-14)
 
 
+def test_tau5_is_exactly_zero_on_equal_values_and_mirror_invariant():
+    """Eq. (25) in floating point, formed with mirror points paired: any
+    stencil of five equal finite values gives tau5 = 0 exactly (so the
+    weights are exactly d_k, eqs. (21) and (28)), and a stencil and its
+    mirror image give the same bits.  Pins the evaluation order: the
+    left-to-right sum e - 4d + 6c - 4b + a leaves a rounding residue for
+    most values (3c and 6c are not exact)."""
+    rs = np.random.default_rng(11)
+    vals = np.concatenate([rs.uniform(-1e9, 1e9, 300), rs.normal(size=300),
+                           [1.0 / 3.4, 4.4 * 6e8 / 3.4, 1e-300, 1e300, -0.0]])
+    residue = 0
+    for c in vals:
+        assert oracle.weno_indicators([c] * 5)[5] == 0.0, c
+        assert list(oracle.weno_weights([c] * 5)) == [0.4 / 1.0000000000000002,
+                                                      0.2 / 1.0000000000000002,
+                                                      0.3 / 1.0000000000000002,
+                                                      0.1 / 1.0000000000000002]
+        t2 = c - 4.0 * c + 6.0 * c - 4.0 * c + c
+        residue += t2 != 0.0
+    assert residue > 100
+    for _ in range(200):
+        v = list(rs.normal(size=5) * 10.0 ** rs.integers(-5, 6))
+        assert oracle.weno_indicators(v)[5] == oracle.weno_indicators(v[::-1])[5]
+
+
 def test_indicators_scale_quadratically_and_ignore_constants():
     rs = np.random.default_rng(5)
     v = rs.normal(size=5)
