@@ -336,14 +336,16 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
       for (int side = 0; side < 2; side++) {
         if (!(fail & (1 << side))) continue;
         double* q = side ? qr : ql;
-        if (admissible(q[0], q[2 + NT], q[3 + NT], q[4 + NT])) {
-          n3++;
-        } else {
+        // counted without a branch: a counter picked by a branch ends up
+        // in private (scratch) memory on every face
+        const int ok = admissible(q[0], q[2 + NT], q[3 + NT], q[4 + NT]) ? 1 : 0;
+        if (!ok) {
           const int j = side ? 3 : 2;
 #pragma unroll
           for (int k = 0; k < NC; k++) q[k] = st(axis_comp<NDIM, D>(k), j);
-          n1++;
         }
+        n3 += ok;
+        n1 += 1 - ok;
       }
     }
   }
