@@ -47,7 +47,9 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   constexpr int NF = TL + 1;     // faces along D per tile row
   // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
   __shared__ double sq[NC * TW * NP];
-  __shared__ double sf[(NC + 1) * TW * NF];
+  // face fluxes in the arithmetic's type: the float form's fluxes are
+  // float values, so float storage is exact and frees LDS for occupancy
+  __shared__ T sf[(NC + 1) * TW * NF];
   __shared__ int s_status;
   __shared__ int s_skip;
 
@@ -121,8 +123,8 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
       mys += nf;
     }
 #pragma unroll
-    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
-    sf[fidx(NC, w, j)] = us;
+    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = T(F[k]);
+    sf[fidx(NC, w, j)] = T(us);
   }
   if (g.stats && g.mood) {
     const unsigned long long b3 = __ballot(my3 != 0);
@@ -154,10 +156,10 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
 #pragma unroll
     for (int k = 0; k < NC; k++) {
       const int kc = axis_comp<NDIM, D>(k);
-      double r = -(sf[fidx(k, w, j + 1)] - sf[fidx(k, w, j)]) / dx;
+      double r = -(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])) / dx;
       if (k >= 3 + (NDIM - 1)) {
         const double phi = sq[lidx(kc, w, j + 3)];
-        r = r + phi * (sf[fidx(NC, w, j + 1)] - sf[fidx(NC, w, j)]) / dx;
+        r = r + phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])) / dx;
       }
       double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
@@ -188,7 +190,9 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   constexpr int NF = TL + 1;     // faces along D per tile row
   // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
   __shared__ double sq[NC * TW * NP];
-  __shared__ double sf[(NC + 1) * TW * NF];
+  // face fluxes in the arithmetic's type: the float form's fluxes are
+  // float values, so float storage is exact and frees LDS for occupancy
+  __shared__ T sf[(NC + 1) * TW * NF];
   __shared__ int s_status;
   __shared__ int s_skip;
   // learned weights: network + one inference tile per wave
@@ -278,8 +282,8 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
       my1 += n1;
     }
 #pragma unroll
-    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = F[k];
-    sf[fidx(NC, w, j)] = us;
+    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = T(F[k]);
+    sf[fidx(NC, w, j)] = T(us);
   }
   if (g.stats) {
     if (g.mood) {
@@ -303,10 +307,10 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
 #pragma unroll
     for (int k = 0; k < NC; k++) {
       const int kc = axis_comp<NDIM, D>(k);
-      double r = -(sf[fidx(k, w, j + 1)] - sf[fidx(k, w, j)]) / dx;
+      double r = -(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])) / dx;
       if (k >= 3 + (NDIM - 1)) {
         const double phi = sq[lidx(kc, w, j + 3)];
-        r = r + phi * (sf[fidx(NC, w, j + 1)] - sf[fidx(NC, w, j)]) / dx;
+        r = r + phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])) / dx;
       }
       double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
