@@ -391,11 +391,13 @@ __global__ void cfl_finalize_kernel(unsigned long long* maxbits, double cfl,
 // ---------------------------------------------------------------------------
 template <int NDIM, int D>
 struct TileShape;
-// x sweeps: 63 cells x 4 rows -> 64 faces per row, one per lane
+// x sweeps: 31 cells x 8 rows -> 32 faces per row, two rows per wave (a
+// shorter halo per row than 63 x 4 costs less than the extra rows; 15 x 16
+// was slower again)
 template <int NDIM>
 struct TileShape<NDIM, 0> {
-  static constexpr int TL = NDIM == 1 ? 255 : 63;
-  static constexpr int TW = NDIM == 1 ? 1 : 4;
+  static constexpr int TL = NDIM == 1 ? 255 : 31;
+  static constexpr int TW = NDIM == 1 ? 1 : 8;
 };
 // y / z sweeps: 16 x-consecutive columns x 15 cells -> 256 faces
 template <int NDIM>
