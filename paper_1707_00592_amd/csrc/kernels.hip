@@ -2,6 +2,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "sweep.hpp"
 
@@ -13,6 +15,19 @@ struct LdsStencil {
   int cstride, pstride;
   __device__ __forceinline__ double operator()(int c, int j) const {
     return base[c * cstride + j * pstride];
+  }
+};
+
+// The same with the two material rows (Gamma, Pi) stored before the others:
+// base points at component 0, which is row 2; Gamma and Pi sit NC rows
+// before their component number.
+template <int NC>
+struct LdsStencilMatFirst {
+  const double* base;  // component 0 (row 2), position 0
+  int cstride, pstride;
+  __device__ __forceinline__ double operator()(int c, int j) const {
+    const int r = c >= NC - 2 ? c - NC : c;
+    return base[r * cstride + j * pstride];
   }
 };
 
@@ -45,11 +60,25 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   constexpr int NC = 4 + NDIM;
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
-  // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
-  __shared__ double sq[NC * TW * NP];
-  // face fluxes in the arithmetic's type: the float form's fluxes are
-  // float values, so float storage is exact and frees LDS for occupancy
-  __shared__ T sf[(NC + 1) * TW * NF];
+  static_assert(TW * NF == NTHR, "one face per thread");
+  // One LDS buffer, two phases.  Faces read the staged primitives sq; the
+  // cells read the face values sf (fluxes and u*, in the arithmetic's type:
+  // the float form's fluxes are float values, so float storage is exact)
+  // and only the Gamma and Pi rows of sq.  In 3D (ALIAS) the rows are stored
+  // in the order (Gamma, Pi, rho, u..., p), sf starts after the first two
+  // and overwrites the others once every face is evaluated (33 -> 21 KB per
+  // FP64 workgroup, 4 -> 5 waves per SIMD); in 1D and 2D registers bound the
+  // occupancy anyway, the rows keep the component order and sf follows sq.
+  // Layouts: D = 0 -> [row][w][p]; D > 0 -> [row][p][w].
+  constexpr bool ALIAS = NDIM == 3;
+  constexpr int QROW = TW * NP;
+  constexpr int SQ_BYTES = NC * QROW * 8;
+  constexpr int SF_OFF = ALIAS ? 2 * QROW * 8 : SQ_BYTES;
+  constexpr int SF_BYTES = (NC + 1) * TW * NF * (int)sizeof(T);
+  constexpr int LDS_BYTES = SQ_BYTES > SF_OFF + SF_BYTES ? SQ_BYTES : SF_OFF + SF_BYTES;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
+  double* const sq = reinterpret_cast<double*>(lds);
+  T* const sf = reinterpret_cast<T*>(lds + SF_OFF);
   __shared__ int s_status;
   __shared__ int s_skip;
 
@@ -73,7 +102,8 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   if (s_skip) return;
 
   auto lidx = [](int c, int w, int p) {
-    return D == 0 ? (c * TW + w) * NP + p : (c * NP + p) * TW + w;
+    const int r = !ALIAS ? c : c >= NC - 2 ? c - (NC - 2) : c + 2;
+    return D == 0 ? (r * TW + w) * NP + p : (r * NP + p) * TW + w;
   };
   auto fidx = [](int k, int w, int j) {
     return D == 0 ? (k * TW + w) * NF + j : (k * NF + j) * TW + w;
@@ -100,31 +130,41 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
 
-  // 2. faces
+  // 2. faces: thread tid owns face (w, j); with ALIAS the values wait in
+  // registers until every face has read sq
   int my3 = 0, my1 = 0, mys = 0;
-  for (int f = tid; f < TW * NF; f += NTHR) {
-    const int w = D == 0 ? f / NF : f % TW;
-    const int j = D == 0 ? f % NF : f / TW;
-    const int64_t a = a0 + w;
-    const int64_t gl = l0 + j;  // face index along D (between gl-1 and gl)
-    if (a >= geo.nA || gl > geo.nL) continue;
-    LdsStencil st;
-    st.base = &sq[lidx(0, w, j)];
+  const int fw = D == 0 ? tid / NF : tid % TW;
+  const int fj = D == 0 ? tid % NF : tid / TW;
+  const bool fvalid = a0 + fw < geo.nA && l0 + fj <= geo.nL;
+  double F[NC], us;
+  if (fvalid) {
+    const int64_t gl = l0 + fj;  // face index along D (between gl-1 and gl)
+    std::conditional_t<ALIAS, LdsStencilMatFirst<NC>, LdsStencil> st;
+    st.base = &sq[lidx(0, fw, fj)];
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
-    double F[NC], us;
     int n3, n1, nf;
     face_flux<T, NDIM, D>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nf);
     // the face on a tile boundary is evaluated by both tiles; count it once
     // (in the tile to its right, or the last tile for the domain's last face)
-    if (j < TL || gl == geo.nL) {
+    if (fj < TL || gl == geo.nL) {
       my3 += n3;
       my1 += n1;
       mys += nf;
     }
+    if constexpr (!ALIAS) {
 #pragma unroll
-    for (int k = 0; k < NC; k++) sf[fidx(k, w, j)] = T(F[k]);
-    sf[fidx(NC, w, j)] = T(us);
+      for (int k = 0; k < NC; k++) sf[fidx(k, fw, fj)] = T(F[k]);
+      sf[fidx(NC, fw, fj)] = T(us);
+    }
+  }
+  if constexpr (ALIAS) {
+    __syncthreads();
+    if (fvalid) {
+#pragma unroll
+      for (int k = 0; k < NC; k++) sf[fidx(k, fw, fj)] = T(F[k]);
+      sf[fidx(NC, fw, fj)] = T(us);
+    }
   }
   if (g.stats && g.mood) {
     const unsigned long long b3 = __ballot(my3 != 0);
