@@ -31,7 +31,7 @@ def ctx(lib):
     return lib.Context(0)
 
 
-@pytest.mark.parametrize("shape", [(300,), (150, 70), (20, 18, 17)])
+@pytest.mark.parametrize("shape", [(300,), (150, 70), (20, 18, 17), (70, 17, 33)])
 def test_fp32_rhs_within_bound(lib, ctx, shape):
     p = wl.random_two_phase(shape, seed=11)
     og = oracle.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)

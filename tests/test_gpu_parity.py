@@ -63,7 +63,7 @@ def ctx(lib):
 CASES = [
     ((300,), 0), ((300,), 1), ((300,), 2), ((7,), 0), ((1,), 0),
     ((150, 70), 0), ((150, 70), 1), ((150, 70), 2), ((64, 15), 0),
-    ((20, 18, 17), 0), ((20, 18, 17), 2),
+    ((20, 18, 17), 0), ((20, 18, 17), 2), ((70, 17, 33), 1),
 ]
 
 
@@ -162,6 +162,28 @@ def test_shock_droplet_3d_steps_match_oracle(lib, ctx):
     for _ in range(4):
         ctx.rk3_step(U, ig, lib.make_opts(), dt)
     _check(U.cpu().numpy(), ref, what="shock-droplet 24^3 x4")
+
+
+def test_random_3d_steps_span_tiles_and_match_oracle(lib, ctx):
+    """Two CFL steps on a 70 x 17 x 33 two-phase field with periodic ends:
+    3, 2 and 3 tiles along x, y and z, each with a ragged last tile, through
+    all three stage modes of the 3D kernels; the MOOD cascade acts on every
+    axis (the oracle's counts: order 3 on 0/2/2 faces, order 1 on 3/305/48),
+    and the same faces fall back."""
+    torch = _torch()
+    p = wl.random_two_phase((70, 17, 33), seed=0)
+    og, ig = _grids(p, 1)
+    ref, _, _, st = oracle.run(p.U, og, oracle.make_opts(), nsteps=2)
+    assert st.status == 0 and sum(st.o1[:3]) > 0
+    U = _dev(p.U)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s = lib.new_stats()
+    for _ in range(2):
+        ctx.rk3_step(U, ig, lib.make_opts(), dt, s)
+    s = lib.read_stats(s)
+    assert s.status == 0
+    assert list(s.o3[:3]) == list(st.o3[:3]) and list(s.o1[:3]) == list(st.o1[:3])
+    _check(U.cpu().numpy(), ref, what="random 70x17x33 x2")
 
 
 def test_fixed_dt_step_matches_oracle(lib, ctx):
