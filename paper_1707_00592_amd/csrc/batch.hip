@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void batch_dt_kernel(const double* U, int64_t 
   __shared__ double red[256];
   red[threadIdx.x] = m;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (unsigned o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
       const double x = red[threadIdx.x + o];
       if (x > red[threadIdx.x] || x != x) red[threadIdx.x] = x;
