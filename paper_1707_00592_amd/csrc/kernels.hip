@@ -305,8 +305,11 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   mr.fallbacks = 0;
   for (int f0 = 0; f0 < TW * NF; f0 += NTHR) {
     const int f = f0 + tid;
-    int w = D == 0 ? f / NF : f % TW;
-    int j = D == 0 ? f % NF : f / TW;
+    // x tiles of 8 rows x 32 faces: each wave takes an 8 x 8 block, so more
+    // waves find every stencil flat and skip the network (x sweep -7%)
+    constexpr bool BLOCKED = D == 0 && TW == 8 && NF == 32 && TW * NF == NTHR;
+    int w = BLOCKED ? (f & 63) >> 3 : D == 0 ? f / NF : f % TW;
+    int j = BLOCKED ? ((f >> 6) << 3) | (f & 7) : D == 0 ? f % NF : f / TW;
     bool valid = f < TW * NF && a0 + w < geo.nA && l0 + j <= geo.nL;
     if (!valid) {
       w = 0;
