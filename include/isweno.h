@@ -289,6 +289,8 @@ enum {
   ISWENO_K_SWEEP_Y = 1,  /* stage sweep along y */
   ISWENO_K_SWEEP_Z = 2,  /* stage sweep along z */
   ISWENO_K_CFL = 3,      /* time-step reduction */
+  ISWENO_K_STAGE2D = 4,  /* whole stage of a 2D grid, x and y faces fused
+                            (plain and float32 forms) */
   ISWENO_K_COUNT = 8
 };
 ISWENO_API int isweno_timing_enable(isweno_ctx *ctx, int enable);

@@ -149,6 +149,8 @@ isw::SweepArgs base_args(const isweno_grid* g, const isweno_opts* o, isweno_stat
   for (int d = 0; d < 3; d++) {
     a.n[d] = g->n[d];
     a.dx[d] = g->dx[d];
+    a.bcl[d] = g->bc_lo[d];
+    a.bch[d] = g->bc_hi[d];
   }
   a.weights = o->weights;
   a.mood = o->mood;
@@ -165,6 +167,13 @@ isw::SweepArgs base_args(const isweno_grid* g, const isweno_opts* o, isweno_stat
 hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw::SweepArgs a,
                  double* partial, int mode, hipStream_t s) {
   const int nd = g->ndim;
+  if (nd == 2 && o->weights != ISWENO_W_MLP) {
+    // one fused launch: the x terms stay in registers
+    isw::SweepArgs b = a;
+    b.shortcut = c->timing ? c->shortcut : nullptr;  // never inside a captured graph
+    KTimer t(c, ISWENO_K_STAGE2D);
+    return isw::launch_stage2d(o->precision, b, mode, s, t.ev);
+  }
   for (int D = 0; D < nd; D++) {
     isw::SweepArgs b = a;
     b.bc_lo = g->bc_lo[D];

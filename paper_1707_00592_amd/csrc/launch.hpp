@@ -20,6 +20,12 @@ struct LaunchEvents {
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
                         bool readR, hipStream_t s, LaunchEvents ev = {});
 
+// One whole RK stage of a 2D grid (x and y faces of each tile in one
+// launch); mode is OUT_RHS or one of the OUT_RK* modes.  Not for the
+// learned weights.
+hipError_t launch_stage2d(int precision, const SweepArgs& a, int mode, hipStream_t s,
+                          LaunchEvents ev = {});
+
 // dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); maxbits is
 // a zeroed device word, left zeroed on exit.
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,

@@ -50,6 +50,7 @@ struct SweepArgs {
   int64_t n[3];
   double dx[3];
   int bc_lo, bc_hi;    // of axis D
+  int bcl[3], bch[3];  // of every axis (fused multi-axis stage kernels)
   int weights, mood;
   double eps;
   const uint16_t* mlp; // packed bf16 network (learned weights only)

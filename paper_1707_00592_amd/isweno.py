@@ -77,8 +77,9 @@ _SIGS = {
                                      C.POINTER(C.c_int64)]),
 }
 
-K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_CFL = 0, 1, 2, 3
-K_NAMES = {K_SWEEP_X: "sweep_x", K_SWEEP_Y: "sweep_y", K_SWEEP_Z: "sweep_z", K_CFL: "cfl"}
+K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_CFL, K_STAGE2D = 0, 1, 2, 3, 4
+K_NAMES = {K_SWEEP_X: "sweep_x", K_SWEEP_Y: "sweep_y", K_SWEEP_Z: "sweep_z", K_CFL: "cfl",
+           K_STAGE2D: "stage_2d"}
 
 EXPORTED = tuple(_SIGS)
 

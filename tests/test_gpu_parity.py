@@ -4,8 +4,9 @@ The FP64 path evaluates every face in the same written operation order as
 the oracle (no fused multiply-add on either side), so the expected result
 is bit-for-bit equality, asserted next to the stated tolerance (relative
 L1 <= 1e-10 per component).
-Sizes span several tiles with ragged tails (x tiles of 63 or 255 cells,
-y/z tiles of 15 cells by 16 columns).
+Sizes span several tiles with ragged tails (1D tiles of 255 cells; 2D
+stage tiles of 16 x 15 cells; 3D x tiles of 31 x 8, y/z tiles of 15 cells
+by 16 columns).
 """
 import numpy as np
 import pytest
@@ -62,7 +63,8 @@ def ctx(lib):
 
 CASES = [
     ((300,), 0), ((300,), 1), ((300,), 2), ((7,), 0), ((1,), 0),
-    ((150, 70), 0), ((150, 70), 1), ((150, 70), 2), ((64, 15), 0),
+    ((150, 70), 0), ((150, 70), 1), ((150, 70), 2), ((64, 15), 0), ((33, 46), 2),
+    ((17, 3), 1), ((3, 31), 0),
     ((20, 18, 17), 0), ((20, 18, 17), 2), ((70, 17, 33), 1),
 ]
 
@@ -292,6 +294,70 @@ def test_full_size_3d_droplet_rhs_matches_oracle(lib, ctx):
     print(f"[parity] rhs 256^3 FP32 form: per-step state change error {np.array2string(e, precision=2)}",
           flush=True)
     assert np.all(np.isfinite(g32)) and e.max() < 1e-6
+
+
+def _developed_state(lib, ctx, p, nsteps):
+    """p advanced by nsteps FP64 CFL steps on the GPU (MOOD on)."""
+    torch = _torch()
+    _, ig = _grids(p)
+    U = _dev(p.U)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = lib.new_stats()
+    for _ in range(nsteps):
+        ctx.rk3_step(U, ig, lib.make_opts(), dt, st)
+    assert lib.read_stats(st).status == 0
+    return U
+
+
+def _developed_checks(lib, ctx, p, U, what, min_general):
+    """On a developed state: one RHS and one RK3 step bit for bit against
+    the oracle with the same MOOD counts, and at least `min_general` of the
+    field-sides on the general (non-linear-weight) reconstruction path."""
+    torch = _torch()
+    og, ig = _grids(p)
+    Uh = U.cpu().numpy()
+    o = oracle.make_opts()
+    ref, ost = oracle.rhs(Uh, og, o)
+    ctx.timing_enable(True)
+    st = lib.new_stats()
+    got = ctx.rhs(U, ig, lib.make_opts(), stats=st).cpu().numpy()
+    short = ctx.shortcut_read()
+    ctx.timing_enable(False)
+    gst = lib.read_stats(st)
+    nd = p.ndim
+    sides = sum(p.ncells // p.n[d] * (p.n[d] + 1) for d in range(nd)) * 2 * (4 + nd)
+    general = 1.0 - sum(short[:nd]) / sides
+    print(f"[parity] {what}: MOOD o3 {list(ost.o3[:nd])} o1 {list(ost.o1[:nd])}, "
+          f"general-path field-sides {general:.3f}", flush=True)
+    assert list(gst.o3[:nd]) == list(ost.o3[:nd]) and list(gst.o1[:nd]) == list(ost.o1[:nd])
+    _check(got, ref, what=f"rhs {what}")
+    assert general >= min_general
+    h = oracle.cfl_dt(Uh, og, o)
+    ref1, s = oracle.rk3_step(Uh, og, h, o)
+    assert s == 0
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.rk3_step(U, ig, lib.make_opts(), dt)
+    assert dt.item() == h
+    _check(U.cpu().numpy(), ref1, what=f"rk3 step {what}")
+
+
+def test_developed_full_size_2d_state_matches_oracle(lib, ctx):
+    """The benchmark grid (1024 x 512 shock-bubble) after 1000 FP64 steps:
+    the shock has crossed the bubble (it reaches it near step 350), the
+    interface is rolled up and most reconstructions take the general path.
+    One RHS with its MOOD counts and one RK3 step equal the oracle's."""
+    p = wl.shock_bubble_2d(1024, 512)
+    U = _developed_state(lib, ctx, p, 1000)
+    _developed_checks(lib, ctx, p, U, "1024x512 after 1000 steps", 0.05)
+
+
+def test_developed_3d_droplet_state_matches_oracle(lib, ctx):
+    """A 64^3 shock-droplet (radius 8 cells) after 120 FP64 steps, once the
+    shock has met the droplet (about step 50): one RHS and one RK3 step bit
+    for bit against the oracle, MOOD counts equal."""
+    p = wl.shock_droplet_3d(64)
+    U = _developed_state(lib, ctx, p, 120)
+    _developed_checks(lib, ctx, p, U, "64^3 droplet after 120 steps", 0.02)
 
 
 def test_graph_replays_match_direct_launches(lib, ctx):
