@@ -7,32 +7,10 @@
 #include <string>
 #include <vector>
 
+#include "ctx.hpp"
 #include "isweno.h"
 #include "launch.hpp"
 #include "sweep.hpp"
-
-struct isweno_ctx {
-  int device = 0;
-  int ncu = 256;
-  double* ws = nullptr;          // two state-sized buffers (U1, U2)
-  size_t ws_bytes = 0;
-  unsigned long long* maxbits = nullptr;  // time-step reduction word
-  unsigned long long* shortcut = nullptr;  // 256 x 3 reconstruction-shortcut counters (timing only)
-  // kernel timing
-  struct Rec {
-    int kind;
-    hipEvent_t a, b;
-  };
-  bool timing = false;
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-  double total_ms[ISWENO_K_COUNT] = {};
-  int64_t launches[ISWENO_K_COUNT] = {};
-  // RK3 steps captured as HIP graphs, keyed by everything a captured step
-  // bakes in (pointers, grid, options, workspace)
-  hipStream_t cap = nullptr;
-  std::map<std::string, hipGraphExec_t> graphs;
-};
 
 namespace {
 
@@ -86,7 +64,7 @@ void drain_timing(isweno_ctx* c) {
 
 }  // namespace
 
-namespace {
+namespace isw {
 
 int check_grid(const isweno_grid* g) {
   if (!g || g->ndim < 1 || g->ndim > 3 || g->reserved != 0) return ISWENO_ERR_ARG;
@@ -120,6 +98,13 @@ int check_opts(const isweno_opts* o) {
   }
   return ISWENO_OK;
 }
+
+}  // namespace isw
+
+namespace {
+
+using isw::check_grid;
+using isw::check_opts;
 
 int64_t ncells(const isweno_grid* g) { return g->n[0] * g->n[1] * g->n[2]; }
 
@@ -273,6 +258,7 @@ void isweno_destroy(isweno_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->maxbits) (void)hipFree(c->maxbits);
   if (c->shortcut) (void)hipFree(c->shortcut);
+  if (c->mlp_part) (void)hipFree(c->mlp_part);
   drain_timing(c);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;

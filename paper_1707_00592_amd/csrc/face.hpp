@@ -390,6 +390,53 @@ __device__ __forceinline__ void star_flux(const T* q, T Sk, T Ss, T* F,
   us = qdiv<T>(Ss * (Sk - un), den);
 }
 
+// The products 0 * F*_k and 0 * u*_k of eq. (14) for a star state whose
+// weight is zero: signed zeros (or NaN for a non-finite state).  Formed
+// with star_flux's operations up to its division; a quotient's sign is the
+// sign of numerator times denominator, so (0 * num) * den is 0 * (num / den)
+// for every finite num and den != 0 (and den == 0 takes the physical flux,
+// as star_flux does).  FP64 only.
+template <int NT>
+__device__ __forceinline__ void star_zeros(const double* q, double Sk, double Ss, double* Z,
+                                           double& zus) {
+  constexpr int NC = 5 + NT;
+  const double rho = q[0], un = q[1], p = q[2 + NT], G = q[3 + NT], P = q[4 + NT];
+  double ke = un * un;
+#pragma unroll
+  for (int t = 0; t < NT; t++) ke = ke + q[2 + t] * q[2 + t];
+  const double E = G * p + P + 0.5 * rho * ke;
+  double Uk[NC], Fk[NC];
+  Uk[0] = rho;
+  Uk[1] = rho * un;
+#pragma unroll
+  for (int t = 0; t < NT; t++) Uk[2 + t] = rho * q[2 + t];
+  Uk[2 + NT] = E;
+  Uk[3 + NT] = G;
+  Uk[4 + NT] = P;
+  Fk[0] = rho * un;
+  Fk[1] = rho * un * un + p;
+#pragma unroll
+  for (int t = 0; t < NT; t++) Fk[2 + t] = rho * un * q[2 + t];
+  Fk[2 + NT] = (E + p) * un;
+  Fk[3 + NT] = G * un;
+  Fk[4 + NT] = P * un;
+  const double den = Sk - Ss;
+  if (den == 0.0) {
+#pragma unroll
+    for (int k = 0; k < NC; k++) Z[k] = 0.0 * Fk[k];
+    zus = 0.0 * un;
+    return;
+  }
+  const double pk = p + rho * (Sk - un) * (Ss - un);
+  const double sp = Sk * pk;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    const double Dk = (k == 1) ? 1.0 : ((k == 2 + NT) ? Ss : 0.0);
+    Z[k] = (0.0 * (Ss * (Sk * Uk[k] - Fk[k]) + sp * Dk)) * den;
+  }
+  zus = (0.0 * (Ss * (Sk - un))) * den;
+}
+
 template <typename T, int NT>
 __device__ __forceinline__ void hllc(const T* ql, const T* qr, T* F, T& us) {
   constexpr int NC = 5 + NT;
@@ -414,6 +461,24 @@ __device__ __forceinline__ void hllc(const T* ql, const T* qr, T* F, T& us) {
 #pragma unroll
     for (int k = 0; k < NC; k++) qs[k] = left ? ql[k] : qr[k];
     star_flux<T, NT>(qs, left ? Sl : Sr, Ss, F, us);
+    if constexpr (sizeof(T) == 8) {
+      // Eq. (14) as written adds the other star state times zero.  That
+      // changes no value, only the sign of a flux component that is exactly
+      // zero (a transverse momentum flux where u_t = 0, say), so the FP64
+      // path adds it where the selected state has such a component.
+      bool z = us == T(0);
+#pragma unroll
+      for (int k = 0; k < NC; k++) z = z || F[k] == T(0);
+      if (z) {
+        T qo[NC], Z[NC], zus;
+#pragma unroll
+        for (int k = 0; k < NC; k++) qo[k] = left ? qr[k] : ql[k];
+        star_zeros<NT>(qo, left ? Sr : Sl, Ss, Z, zus);
+#pragma unroll
+        for (int k = 0; k < NC; k++) F[k] = F[k] + Z[k];
+        us = us + zus;
+      }
+    }
   } else {
     T Fl[NC], Fr[NC], usl, usr;
     star_flux<T, NT>(ql, Sl, Ss, Fl, usl);

@@ -2,6 +2,7 @@
 // Adam, and packing for the stage kernel (isweno_mlp_*).
 #include <hip/hip_runtime.h>
 
+#include "ctx.hpp"
 #include "isweno.h"
 #include "mlp.hpp"
 #include "sweep.hpp"
@@ -372,8 +373,6 @@ int grad_blocks(int64_t n) {
   if (b < 1) b = 1;
   return (int)b;
 }
-float* g_part = nullptr;  // per-process partial buffer (grown on demand)
-int g_part_blocks = 0;
 }  // namespace
 
 extern "C" {
@@ -383,10 +382,12 @@ int isweno_mlp_samples(isweno_ctx* ctx, const isweno_grid* g, const isweno_opts*
                        void* stream) {
   if (!ctx || !g || !o || !U || !X || !Y || !count || max_samples < 1 || stride < 1)
     return ISWENO_ERR_ARG;
-  if (g->ndim < 1 || g->ndim > 3) return ISWENO_ERR_ARG;
-  for (int d = 0; d < g->ndim; d++)
-    if (g->n[d] < 1 || g->bc_lo[d] < 0 || g->bc_lo[d] > 2 || g->bc_hi[d] < 0 || g->bc_hi[d] > 2)
-      return ISWENO_ERR_ARG;
+  int r;
+  // the same grid and option checks as the solver: the sampler stages the
+  // same ghost cells (a reflective end needs at least 3 cells)
+  if ((r = isw::check_grid(g)) != ISWENO_OK) return r;
+  if ((r = isw::check_opts(o)) != ISWENO_OK) return r;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t N = g->n[0] * g->n[1] * g->n[2];
   int64_t total = 0;
@@ -415,6 +416,7 @@ int isweno_mlp_samples(isweno_ctx* ctx, const isweno_grid* g, const isweno_opts*
 int isweno_mlp_infer(isweno_ctx* ctx, const uint16_t* packed, const float* X, int64_t n,
                      float* out, void* stream) {
   if (!ctx || !packed || !X || !out || n < 0) return ISWENO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   if (n == 0) return ISWENO_OK;
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffffLL) return ISWENO_ERR_ARG;
@@ -427,6 +429,7 @@ int isweno_mlp_infer(isweno_ctx* ctx, const uint16_t* packed, const float* X, in
 int isweno_mlp_forward(isweno_ctx* ctx, const float* P, const float* X, int64_t n, float* out,
                        void* stream) {
   if (!ctx || !P || !X || !out || n < 0) return ISWENO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   if (n == 0) return ISWENO_OK;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(isw::mlp_forward_kernel, dim3(grad_blocks(n)), dim3(64 * isw::MLP_WAVES), 0,
@@ -437,30 +440,35 @@ int isweno_mlp_forward(isweno_ctx* ctx, const float* P, const float* X, int64_t 
 int isweno_mlp_loss_grad(isweno_ctx* ctx, const float* P, const float* X, const float* Y,
                          const float* Cc, int64_t n, float* loss, float* grad, void* stream) {
   if (!ctx || !P || !X || !Y || !loss || !grad || n < 1) return ISWENO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int nb = grad_blocks(n);
-  if (nb > g_part_blocks) {
-    if (g_part) {
+  // partial gradients in the context's own buffer (grown on demand; calls
+  // on one context do not overlap, see isweno.h)
+  if (nb > ctx->mlp_part_blocks) {
+    if (ctx->mlp_part) {
       if (hipDeviceSynchronize() != hipSuccess) return ISWENO_ERR_DEVICE;
-      (void)hipFree(g_part);
-      g_part = nullptr;
-      g_part_blocks = 0;
+      (void)hipFree(ctx->mlp_part);
+      ctx->mlp_part = nullptr;
+      ctx->mlp_part_blocks = 0;
     }
-    if (hipMalloc(&g_part, sizeof(float) * (size_t)nb * (isw::MLP_NPARAM + 1)) != hipSuccess)
+    if (hipMalloc(&ctx->mlp_part, sizeof(float) * (size_t)nb * (isw::MLP_NPARAM + 1)) !=
+        hipSuccess)
       return ISWENO_ERR_DEVICE;
-    g_part_blocks = nb;
+    ctx->mlp_part_blocks = nb;
   }
   hipLaunchKernelGGL(isw::mlp_grad_kernel, dim3(nb), dim3(64 * isw::MLP_WAVES), 0, s, P, X, Y, Cc,
-                     n, g_part);
+                     n, ctx->mlp_part);
   if (hipGetLastError() != hipSuccess) return ISWENO_ERR_DEVICE;
   hipLaunchKernelGGL(isw::mlp_reduce_kernel, dim3((isw::MLP_NPARAM + 1 + 255) / 256), dim3(256), 0,
-                     s, g_part, nb, grad, loss);
+                     s, ctx->mlp_part, nb, grad, loss);
   return hipGetLastError() == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
 }
 
 int isweno_mlp_adam(isweno_ctx* ctx, float* P, const float* G, float* M, float* V, int32_t step,
                     float lr, float beta1, float beta2, float eps, void* stream) {
   if (!ctx || !P || !G || !M || !V || step < 1) return ISWENO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
   hipLaunchKernelGGL(isw::mlp_adam_kernel, dim3((isw::MLP_NPARAM + 255) / 256), dim3(256), 0, s, P,
@@ -470,6 +478,7 @@ int isweno_mlp_adam(isweno_ctx* ctx, float* P, const float* G, float* M, float* 
 
 int isweno_mlp_pack(isweno_ctx* ctx, const float* P, uint16_t* packed, void* stream) {
   if (!ctx || !P || !packed) return ISWENO_ERR_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(isw::mlp_pack_kernel, dim3((isw::MLP_NPARAM + 255) / 256), dim3(256), 0, s, P,
                      packed);

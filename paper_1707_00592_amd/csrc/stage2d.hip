@@ -53,9 +53,25 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   __shared__ int s_skip;
 
   const int64_t nx = g.n[0], ny = g.n[1], N = nx * ny;
-  const int64_t ntx = (nx + TX - 1) / TX;
-  const int64_t gx0 = (int64_t)(blockIdx.x % ntx) * TX;
-  const int64_t gy0 = (int64_t)(blockIdx.x / ntx) * TY;
+  // Tile order.  The hardware deals workgroups to its 8 XCDs in turn
+  // (workgroup b to XCD b mod 8), each XCD with its own L2.  XCD x's
+  // workgroups take one contiguous run of tiles, in an order that walks
+  // along tile rows (x-neighbours, whose halo lines overlap, share an L2)
+  // and visits the rows as 0, 8, 16, ..., 1, 9, ... (every XCD gets rows
+  // spread over the whole height, so fronts stay evenly shared).
+  const int64_t ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int64_t ntiles = ntx * nty;
+  const int64_t xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int64_t per = ntiles >> 3, extra = ntiles & 7;
+  const int64_t pos = xcd * per + (xcd < extra ? xcd : extra) + k;
+  const int64_t prow = pos / ntx;
+  int64_t cls = 0, first = 0;  // rows cls, cls + 8, ... hold positions first ...
+  while (prow >= first + ((nty - cls + 7) >> 3)) {
+    first += (nty - cls + 7) >> 3;
+    cls++;
+  }
+  const int64_t gx0 = (pos % ntx) * TX;
+  const int64_t gy0 = (cls + 8 * (prow - first)) * TY;
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_status = ST_OK;

@@ -196,6 +196,29 @@ def test_samples_match_reference_weights(lib, ctx):
             np.testing.assert_allclose(Xh[row, :6], feat, rtol=1e-5, atol=1e-6)
 
 
+def test_samples_argument_errors(lib, ctx):
+    """isweno_mlp_samples takes the solver's grid and option checks: a
+    reflective end on an axis of fewer than 3 cells (whose ghost cells would
+    fall outside the grid), an unused axis of more than one cell and an
+    unknown weight form are refused before anything is launched."""
+    import torch
+    X = torch.zeros((64, 8), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((64, 8), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    U = torch.zeros((5, 2), dtype=torch.float64, device="cuda")
+    refl = lib.make_grid((2,), (0.1,), 2, 2)
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.mlp_samples(U, refl, lib.make_opts(), X, Y, 64, 1, cnt)
+    bad = lib.make_grid((2,), (0.1,))
+    bad.n[1] = 3
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.mlp_samples(U, bad, lib.make_opts(), X, Y, 64, 1, cnt)
+    o = lib.make_opts()
+    o.weights = 9
+    with pytest.raises(RuntimeError, match="invalid argument"):
+        ctx.mlp_samples(U, lib.make_grid((2,), (0.1,)), o, X, Y, 64, 1, cnt)
+
+
 def test_training_and_learned_weights_in_the_solver(lib, ctx):
     """Train on faces from plain runs (gas-liquid shock tube and a small
     shock-droplet), then run the shock tube with the learned weights: the

@@ -41,7 +41,9 @@ def _check(got, ref, tol=1e-10, what="", bitwise=True):
     path, bit-for-bit equality, which its fixed operation order gives."""
     assert np.all(np.isfinite(got)), what
     r = _rel_l1(got, ref)
-    same = np.array_equal(got, ref)
+    # bit patterns, so that the sign of every zero is compared as well
+    same = np.array_equal(np.ascontiguousarray(got).view(np.uint64),
+                          np.ascontiguousarray(ref).view(np.uint64))
     print(f"[parity] {what}: bitwise={same} max rel L1={r.max():.3e}", flush=True)
     assert r.max() <= tol, (what, r)
     if bitwise:

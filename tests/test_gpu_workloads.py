@@ -28,7 +28,9 @@ def _grids(p):
 
 
 def _same(got, ref, what):
-    same = np.array_equal(got, ref)
+    # bit patterns, so that the sign of every zero is compared as well
+    same = np.array_equal(np.ascontiguousarray(got).view(np.uint64),
+                          np.ascontiguousarray(ref).view(np.uint64))
     print(f"[workload] {what}: bitwise={same} max abs diff "
           f"{np.abs(got - ref).max():.3e}", flush=True)
     assert np.all(np.isfinite(got)) and same, what
