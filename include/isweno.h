@@ -174,6 +174,25 @@ ISWENO_API int isweno_rk3_step(isweno_ctx *ctx, const isweno_grid *grid,
                     const isweno_opts *opts, double *U, double *dt,
                     isweno_stats *stats, void *stream);
 
+/* isweno_rk3_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same step with the same results, but its intermediate states and
+ * time-step word live in a fixed scratch array of the library (a device
+ * global of 128 MiB plus 256 bytes that every GPU the library runs on holds
+ * until the process ends) instead of the context's workspace, and it
+ * launches its kernels directly (no graph, no timing events).  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ *   - Limit: 2 * nc * N * 8 bytes <= 128 MiB (2D, nc = 6: N <= 1,398,101
+ *     cells; 3D, nc = 7: N <= 1,198,372); larger grids return
+ *     ISWENO_ERR_ARG and enqueue nothing.  Other errors as isweno_rk3_step.
+ *   - The scratch is shared by every call on one GPU and keeps the last
+ *     call's contents; the step clears what must start at zero.  Calls that
+ *     overlap on one GPU (other streams, other contexts, other host threads)
+ *     race on it: order them. */
+ISWENO_API int isweno_rk3_step_noalloc(isweno_ctx *ctx, const isweno_grid *grid,
+                            const isweno_opts *opts, double *U, double *dt,
+                            isweno_stats *stats, void *stream);
+
 /* ---- many independent 1D problems (uneven lengths) ----
  * Problem p owns cells offsets[p] .. offsets[p+1]-1 of a state laid out as
  * U[c*offsets[nprob] + cell], c = 0..4 (1D components), with its own cell

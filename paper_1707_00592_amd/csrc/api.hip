@@ -3,6 +3,7 @@
 
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -148,15 +149,18 @@ isw::SweepArgs base_args(const isweno_grid* g, const isweno_opts* o, isweno_stat
 
 // One evaluation of L on Uin followed by the output step `mode`; the partial
 // sums of the first ndim-1 axes go to `partial` (which may alias the final
-// output buffer, cell by cell).
+// output buffer, cell by cell).  timed = false: no timing events or
+// shortcut counts even while timing is enabled (the allocation-free step).
 hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw::SweepArgs a,
-                 double* partial, int mode, hipStream_t s) {
+                 double* partial, int mode, bool timed, hipStream_t s) {
   const int nd = g->ndim;
+  isweno_ctx* tc = timed ? c : nullptr;
+  unsigned long long* shortcut = timed && c->timing ? c->shortcut : nullptr;
   if (nd == 2 && o->weights != ISWENO_W_MLP) {
     // one fused launch: the x terms stay in registers
     isw::SweepArgs b = a;
-    b.shortcut = c->timing ? c->shortcut : nullptr;  // never inside a captured graph
-    KTimer t(c, ISWENO_K_STAGE2D);
+    b.shortcut = shortcut;  // never inside a captured graph
+    KTimer t(tc, ISWENO_K_STAGE2D);
     return isw::launch_stage2d(o->precision, b, mode, s, t.ev);
   }
   for (int D = 0; D < nd; D++) {
@@ -166,8 +170,8 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
     const bool last = D == nd - 1;
     b.R = partial;
     if (!last) b.Rout = partial;
-    b.shortcut = c->timing ? c->shortcut : nullptr;  // never inside a captured graph
-    KTimer t(c, ISWENO_K_SWEEP_X + D);
+    b.shortcut = shortcut;  // never inside a captured graph
+    KTimer t(tc, ISWENO_K_SWEEP_X + D);
     const hipError_t e = isw::launch_sweep(o->precision, nd, D, b,
                                            last ? mode : isw::OUT_PARTIAL, D > 0, s, t.ev);
     if (e != hipSuccess) return e;
@@ -176,17 +180,16 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
 }
 
 // One RK3 step on stream s: the time step (when cfl > 0), then the three
-// stages.  Uses the workspace as U1 = ws, U2 = ws + nc*N.
+// stages, with the intermediate states in U1 and U2 (nc*N each) and the
+// time-step reduction word maxbits (zero on entry, left zero).
 hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
-                       double* dt, isweno_stats* stats, hipStream_t s) {
-  const size_t sz = (size_t)(4 + g->ndim) * (size_t)ncells(g);
-  double* U1 = c->ws;
-  double* U2 = c->ws + sz;
+                       double* dt, isweno_stats* stats, double* U1, double* U2,
+                       unsigned long long* maxbits, bool timed, hipStream_t s) {
   hipError_t e;
   if (o->cfl > 0.0) {
-    KTimer t(c, ISWENO_K_CFL);
-    if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, c->maxbits, dt,
-                             c->ncu, s, t.ev)) != hipSuccess)
+    KTimer t(timed ? c : nullptr, ISWENO_K_CFL);
+    if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, maxbits, dt, c->ncu,
+                             s, t.ev)) != hipSuccess)
       return e;
   }
   isw::SweepArgs a = base_args(g, o, stats);
@@ -195,15 +198,50 @@ hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o
   // stage 1: U1 = U + dt L(U)
   a.Uin = U;
   a.Uout = U1;
-  if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, s)) != hipSuccess) return e;
+  if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, timed, s)) != hipSuccess) return e;
   // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
   a.Uin = U1;
   a.Uout = U2;
-  if ((e = stage(c, g, o, a, U2, isw::OUT_RK2, s)) != hipSuccess) return e;
+  if ((e = stage(c, g, o, a, U2, isw::OUT_RK2, timed, s)) != hipSuccess) return e;
   // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)); partial sums in U1
   a.Uin = U2;
   a.Uout = U;
-  return stage(c, g, o, a, U1, isw::OUT_RK3, s);
+  return stage(c, g, o, a, U1, isw::OUT_RK3, timed, s);
+}
+
+// Workspace of the context: U1 = ws, U2 = ws + nc*N.
+hipError_t enqueue_rk3_ws(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
+                          double* dt, isweno_stats* stats, hipStream_t s) {
+  const size_t sz = (size_t)(4 + g->ndim) * (size_t)ncells(g);
+  return enqueue_rk3(c, g, o, U, dt, stats, c->ws, c->ws + sz, c->maxbits, true, s);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free step (isweno_rk3_step_noalloc): the
+// time-step reduction word in its first 256 bytes, then U1 and U2.  A device
+// global: every GPU the library runs on holds its own copy from the load of
+// the library's code object until the process ends.  Host code never uses
+// the array's name as an address: scratch_addr() returns this device's copy,
+// looked up once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchStates = (size_t)128 << 20;  // bytes for U1 and U2
+static __device__ __align__(256) unsigned char scratch[256 + kScratchStates];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's scratch (the caller has made `device` current), or null
+// when the runtime cannot resolve the symbol.
+unsigned char* scratch_addr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch_ptr[device];
 }
 
 // Everything a captured RK3 step depends on (compared bytewise).
@@ -236,6 +274,13 @@ int isweno_create(isweno_ctx** out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->ncu = prop.multiProcessorCount;
+  // this device's scratch of the allocation-free step, resolved once here
+  // (with the device current) so that the step itself makes no runtime
+  // lookups
+  if (!scratch_addr(device)) {
+    delete c;
+    return ISWENO_ERR_DEVICE;
+  }
   if (hipMalloc(&c->maxbits, 256) != hipSuccess ||
       hipMemset(c->maxbits, 0, 256) != hipSuccess ||
       hipMalloc(&c->shortcut, kShortcutBytes) != hipSuccess ||
@@ -278,7 +323,8 @@ int isweno_rhs(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, const 
   isw::SweepArgs a = base_args(g, o, stats);
   a.Uin = U;
   a.Rout = dUdt;
-  return stage(c, g, o, a, dUdt, isw::OUT_RHS, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
+  return stage(c, g, o, a, dUdt, isw::OUT_RHS, true, s) == hipSuccess ? ISWENO_OK
+                                                                       : ISWENO_ERR_DEVICE;
 }
 
 int isweno_cfl_dt(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, const double* U,
@@ -313,7 +359,8 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
   // to call, and a graph per value would only be captured to be dropped);
   // otherwise replay the step's graph (captured on first use).
   if (c->timing || o->dt_max > 0.0)
-    return enqueue_rk3(c, g, o, U, dt, stats, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
+    return enqueue_rk3_ws(c, g, o, U, dt, stats, s) == hipSuccess ? ISWENO_OK
+                                                                  : ISWENO_ERR_DEVICE;
   StepKey k;
   std::memset(&k, 0, sizeof(k));
   k.U = U;
@@ -342,7 +389,7 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return ISWENO_ERR_DEVICE;
-    const hipError_t e = enqueue_rk3(c, g, o, U, dt, stats, c->cap);
+    const hipError_t e = enqueue_rk3_ws(c, g, o, U, dt, stats, c->cap);
     const hipError_t e2 = hipStreamEndCapture(c->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess || !graph) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -354,6 +401,30 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
     c->graphs.emplace(std::move(key), exec);
   }
   return hipGraphLaunch(exec, s) == hipSuccess ? ISWENO_OK : ISWENO_ERR_DEVICE;
+}
+
+int isweno_rk3_step_noalloc(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o,
+                            double* U, double* dt, isweno_stats* stats, void* stream) {
+  int r;
+  if (!c || !U || !dt) return ISWENO_ERR_ARG;
+  if ((r = check_grid(g)) != ISWENO_OK) return r;
+  if ((r = check_opts(o)) != ISWENO_OK) return r;
+  const int64_t N = ncells(g);
+  const int nc = 4 + g->ndim;
+  if ((uint64_t)N > kScratchStates / (2 * sizeof(double) * (size_t)nc)) return ISWENO_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
+  unsigned char* base = scratch_addr(c->device);  // resolved by isweno_create
+  if (!base) return ISWENO_ERR_DEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  auto* maxbits = reinterpret_cast<unsigned long long*>(base);
+  double* U1 = reinterpret_cast<double*>(base + 256);
+  double* U2 = U1 + (size_t)nc * (size_t)N;
+  // the reduction word keeps whatever the previous call on this GPU left:
+  // clear it with a kernel (no memset node, should a caller capture this)
+  if (o->cfl > 0.0 && isw::launch_zero_u64(maxbits, s) != hipSuccess) return ISWENO_ERR_DEVICE;
+  return enqueue_rk3(c, g, o, U, dt, stats, U1, U2, maxbits, false, s) == hipSuccess
+             ? ISWENO_OK
+             : ISWENO_ERR_DEVICE;
 }
 
 int isweno_timing_enable(isweno_ctx* c, int enable) {

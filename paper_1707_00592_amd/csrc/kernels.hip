@@ -536,6 +536,13 @@ hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int 
                         : launch_sweep_p<double, false>(ndim, D, a, mode, readR, s, ev);
 }
 
+__global__ void zero_u64_kernel(unsigned long long* w) { *w = 0ull; }
+
+hipError_t launch_zero_u64(unsigned long long* w, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev) {

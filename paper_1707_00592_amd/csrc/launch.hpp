@@ -32,4 +32,8 @@ hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double*
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev = {});
 
+// *w = 0 by a one-lane kernel (used instead of a memset, which a captured
+// graph should not contain).
+hipError_t launch_zero_u64(unsigned long long* w, hipStream_t s);
+
 }  // namespace isw

@@ -55,6 +55,8 @@ _SIGS = {
     "isweno_rhs": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp, _vp]),
     "isweno_cfl_dt": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp]),
     "isweno_rk3_step": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp, _vp]),
+    "isweno_rk3_step_noalloc": (C.c_int, [_vp, C.POINTER(Grid), C.POINTER(Opts), _vp, _vp, _vp,
+                                          _vp]),
     "isweno_batch_plan_create": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64),
                                            C.POINTER(C.c_double), C.c_int32, C.c_int32,
                                            C.POINTER(_vp)]),
@@ -203,6 +205,14 @@ class Context:
     def rk3_step(self, U, grid: Grid, opts: Opts, dt, stats=None):
         check(load().isweno_rk3_step(self._h, C.byref(grid), C.byref(opts), _ptr(U), _ptr(dt),
                                      _ptr(stats), _stream()), "rk3_step")
+        return U
+
+    def rk3_step_noalloc(self, U, grid: Grid, opts: Opts, dt, stats=None):
+        """isweno_rk3_step without device allocation (library scratch of
+        128 MiB for the intermediate states; see isweno.h)."""
+        check(load().isweno_rk3_step_noalloc(self._h, C.byref(grid), C.byref(opts), _ptr(U),
+                                             _ptr(dt), _ptr(stats), _stream()),
+              "rk3_step_noalloc")
         return U
 
     # ------------------------------------------------------------ timing
