@@ -89,9 +89,12 @@ enum {
   ISWENO_W_MLP = 2       /* learned weights (isweno_mlp_*) for the
                             acoustic, entropy and shear fields, with the
                             eq. (28) weights as fallback (confidence below
-                            the threshold, or a face value outside the range
-                            of the two cells next to the face) and for the
-                            material fields Gamma, Pi throughout */
+                            the threshold, a face value outside the range
+                            of the two cells next to the face, or a face
+                            state that fails the positivity check, which
+                            is redone with them before the MOOD cascade)
+                            and for the material fields Gamma, Pi
+                            throughout */
 };
 
 typedef struct {
@@ -132,7 +135,12 @@ typedef struct {
   uint64_t mlp_fallback[3]; /* ISWENO_W_MLP: per axis, face-fields below
                                the confidence threshold plus face sides
                                outside their cell range, whose learned
-                               weights were replaced */
+                               weights were replaced by those of eq. (28),
+                               plus face sides whose learned state failed
+                               the positivity check of Sec. 3.4 and was
+                               redone with the eq. (28) weights (before the
+                               order-3 / order-1 cascade, which o3 and o1
+                               count) */
   int32_t status;           /* ISWENO_OK, or ISWENO_ERR_NONPHYSICAL once an
                                input cell of any evaluation had rho <= 0,
                                Gamma <= 0, c^2 <= 0 or a non-finite value;

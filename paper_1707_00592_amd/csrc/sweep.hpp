@@ -328,8 +328,18 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
     // Sec. 3.4: redo a failing side without the 3-point stencils, then fall
     // back to the first-order state of eq. (32) (the cell's own primitive
     // state, since R L q_i = q_i).
-    const int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
-                     (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
+    int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
+               (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
+    if (mr && fail) {
+      // learned weights: a failing side is first redone with the plain
+      // 5th-order WENO-IS weights of eq. (28) (counted as a fallback of the
+      // network); the cascade below then starts from that state
+      int nfl = 0;
+      recon<T, NDIM, D>(st, fail, false, W_MODIFIED, T(eps), a, b, bd, gd, ql, qr, nfl);
+      mr->fallbacks += (fail & 1) + (fail >> 1);
+      fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
+             (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
+    }
     if (fail) {
       int nf3 = 0;
       recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);

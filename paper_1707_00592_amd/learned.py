@@ -3,11 +3,10 @@
 Data: face samples that the method itself generates.  Plain WENO-IS runs of
 given problems are snapshotted and isweno_mlp_samples turns every face and
 characteristic field into 8 network inputs plus the eq. (28) weights of both
-sides (the targets).  Samples whose candidate values (eq. (20), on the
-normalised stencil) spread by more than 0.05 of the stencil's range on a
-side, where the weights decide the result, are kept whole; the rest, where
-any convex weights give nearly the same value, is thinned so that the former
-make up a stated share.
+sides (the targets).  Samples whose target weights leave the optimal weights
+d_k (0.4, 0.2, 0.3, 0.1) by more than 0.05 on a side, where the nonlinear
+weights act, are kept whole; the rest is thinned so that the former make up
+a stated share.
 
 Loss: the error of the value the predicted weights reconstruct against the
 value of the target weights (both on the same candidates), plus a
@@ -17,7 +16,8 @@ eq. (28) weights.
 
 Training: full-precision float32 master parameters, bf16 matrix-core
 forward and backward (isweno_mlp_loss_grad), Adam (isweno_mlp_adam), all in
-the library; this module only selects data and loops.
+the library; this module only selects data and loops (none of the method's
+arithmetic is done here).
 """
 from __future__ import annotations
 
@@ -26,6 +26,11 @@ import math
 import numpy as np
 
 from . import isweno
+
+# Optimal weights d_1..d_4 of the four candidate stencils (Sec. 3.3.1), per
+# side, as the targets list them.
+OPTIMAL_WEIGHTS = [0.4, 0.2, 0.3, 0.1]
+
 
 def init_params(seed: int = 1707) -> np.ndarray:
     """He-uniform weights, zero biases; the confidence bias starts at +2."""
@@ -63,28 +68,15 @@ def collect(ctx: isweno.Context, problems, opts: isweno.Opts, steps: int, every:
     return torch.cat(Xs), torch.cat(Ys)
 
 
-def candidates(X):
-    """Candidates of eq. (20) of both sides on the normalised stencils
-    X[:, 0..5]: returns (left [n,4], right [n,4])."""
-    import torch
-
-    def c4(a, b, c, d, e):
-        return torch.stack([0.5 * c + 0.5 * d, -0.5 * b + 1.5 * c,
-                            c / 3.0 + 5.0 * d / 6.0 - e / 6.0,
-                            a / 3.0 - 7.0 * b / 6.0 + 11.0 * c / 6.0], dim=1)
-    x = X
-    return (c4(x[:, 0], x[:, 1], x[:, 2], x[:, 3], x[:, 4]),
-            c4(x[:, 5], x[:, 4], x[:, 3], x[:, 2], x[:, 1]))
-
-
 def stratify(X, Y, share_nontrivial: float = 0.3, seed: int = 1707, limit: int | None = None):
-    """Keeps every sample whose candidates spread by more than 0.05 on a side
-    and enough of the others that the former are `share_nontrivial` of the
-    set (or all of them if there are too few of the others)."""
+    """Keeps every sample whose target weights differ from the optimal
+    weights d_k by more than 0.05 on a side and enough of the others that
+    the former are `share_nontrivial` of the set (or all of them if there
+    are too few of the others)."""
     import torch
-    cl, cr = candidates(X)
-    spread = torch.maximum(cl.amax(1) - cl.amin(1), cr.amax(1) - cr.amin(1))
-    nontriv = spread > 0.05
+    d = torch.tensor(OPTIMAL_WEIGHTS * 2, dtype=Y.dtype, device=Y.device)
+    dev = (Y - d).abs()
+    nontriv = torch.maximum(dev[:, :4].amax(1), dev[:, 4:].amax(1)) > 0.05
     gen = torch.Generator(device="cpu").manual_seed(seed)
     idx_n = torch.nonzero(nontriv).flatten().cpu()
     idx_t = torch.nonzero(~nontriv).flatten().cpu()
@@ -128,20 +120,14 @@ def train(ctx: isweno.Context, X, Y, steps: int = 2000, batch: int = 65536, lr: 
 
 
 def evaluate(ctx: isweno.Context, P, X, Y, conf_threshold: float = 0.5):
-    """Value error of the predicted weights on a set (units of the stencil's
-    range): its mean, the share of samples within 0.005 on both sides, the
-    share the confidence head accepts, and the share of accepted samples
-    that are within 0.005 (precision of the confidence head)."""
+    """The training loss on a set (from isweno_mlp_loss_grad, the labels of
+    the confidence head formed by the kernel) and the share of samples the
+    confidence head accepts at the threshold."""
     import torch
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros(isweno.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    ctx.mlp_loss_grad(P, X, Y, None, loss, grad)
     out = torch.empty((X.shape[0], 9), dtype=torch.float32, device="cuda")
     ctx.mlp_forward(P, X, out)
-    pl = torch.softmax(out[:, :4], dim=1); pr = torch.softmax(out[:, 4:8], dim=1)
-    cl, cr = candidates(X)
-    el = ((pl - Y[:, :4]) * cl).sum(1).abs()
-    er = ((pr - Y[:, 4:]) * cr).sum(1).abs()
-    err = torch.maximum(el, er)
-    ok = err < 0.005
     conf = torch.sigmoid(out[:, 8]) >= conf_threshold
-    acc = float((ok & conf).float().sum() / conf.float().sum().clamp(min=1.0))
-    return {"mean_value_err": float(err.mean()), "frac_within_0.005": float(ok.float().mean()),
-            "frac_confident": float(conf.float().mean()), "confident_precision": acc}
+    return {"loss": float(loss.item()), "frac_confident": float(conf.float().mean())}

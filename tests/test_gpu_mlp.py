@@ -5,9 +5,14 @@ network does in the solver.
 Bounds (bf16 weights and activations carry 8 significant bits):
   * forward logits within 3e-2 * (1 + |z|) of the FP64 network evaluated on
     the same bf16-rounded parameters and inputs;
-  * loss within 2 % and the gradient within 5 % (relative 2-norm, cosine
-    similarity > 0.998) of the FP64 gradient (loss: value error of the
+  * loss within 2 % and the gradient within 1e-2 (relative 2-norm, cosine
+    similarity > 0.9999) of the FP64 gradient (loss: value error of the
     reconstructions the predicted weights give, plus the confidence term);
+    the FP64 reference rounds nothing, while the kernels round the hidden
+    activations and the back-propagated errors to bf16 (relative 2^-9 per
+    value, through three layers forward and back);
+  * every parameter block of the gradient within 1e-2 (relative 2-norm) of a
+    reference that rounds to bf16 where the kernels do;
   * Adam and bf16 packing match their definitions to float32 rounding.
 """
 import numpy as np
@@ -101,11 +106,89 @@ def test_loss_and_gradient_match_reference(lib, ctx):
     print(f"[mlp] loss {float(loss.item()):.6f} ref {lref:.6f}; grad rel {rel:.3e} cos {cos:.6f}",
           flush=True)
     assert abs(float(loss.item()) - lref) <= 0.02 * abs(lref)
-    assert rel < 0.05 and cos > 0.998
+    assert rel < 1e-2 and cos > 0.9999
     # deterministic: a second evaluation gives the same bits
     grad2 = torch.zeros_like(grad)
     ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), _dev(Cc), loss, grad2)
     assert torch.equal(grad, grad2)
+
+
+def _rounded_reference_grad(P, X, Y, Cc):
+    """The loss gradient with the kernels' bf16 roundings and float64
+    everything else: inputs, weights, the hidden activations (after ReLU)
+    and the back-propagated dz, dh2, dh1 rounded to bf16 where the kernels
+    feed them to the matrix cores; biases, logits and the bias gradients
+    unrounded.  Per-sample loss as isweno_mlp_loss_grad defines it (value
+    error of the reconstructions over 0.01, squared, per side, plus the
+    confidence cross-entropy)."""
+    n = X.shape[0]
+    W1 = _bf16(P[:256]).reshape(32, 8).astype(np.float64)
+    b1 = P[256:288].astype(np.float64)
+    W2 = _bf16(P[288:1312]).reshape(32, 32).astype(np.float64)
+    b2 = P[1312:1344].astype(np.float64)
+    W3 = _bf16(P[1344:1632]).reshape(9, 32).astype(np.float64)
+    b3 = P[1632:1641].astype(np.float64)
+    xb = _bf16(X).astype(np.float64)
+    h1 = _bf16(np.maximum(xb @ W1.T + b1, 0.0)).astype(np.float64)
+    h2 = _bf16(np.maximum(h1 @ W2.T + b2, 0.0)).astype(np.float64)
+    z = h2 @ W3.T + b3
+    x = X.astype(np.float64)
+
+    def cands(a, b, c, d, e):
+        return np.stack([0.5 * c + 0.5 * d, -0.5 * b + 1.5 * c,
+                         c / 3 + 5 * d / 6 - e / 6, a / 3 - 7 * b / 6 + 11 * c / 6], axis=1)
+
+    dz = np.zeros((n, 9))
+    for h, cd in enumerate((cands(x[:, 0], x[:, 1], x[:, 2], x[:, 3], x[:, 4]),
+                            cands(x[:, 5], x[:, 4], x[:, 3], x[:, 2], x[:, 1]))):
+        zh = z[:, 4 * h:4 * h + 4]
+        e = np.exp(zh - zh.max(axis=1, keepdims=True))
+        w = e / e.sum(axis=1, keepdims=True)
+        qh = (w * cd).sum(axis=1)
+        qt = (Y[:, 4 * h:4 * h + 4].astype(np.float64) * cd).sum(axis=1)
+        g = 2.0 * (qh - qt) / 0.01 ** 2 / n
+        dz[:, 4 * h:4 * h + 4] = g[:, None] * w * (cd - qh[:, None])
+    dz[:, 8] = (1.0 / (1.0 + np.exp(-z[:, 8])) - Cc) / n
+    dzb = _bf16(dz).astype(np.float64)
+    gW3 = dzb.T @ h2
+    gb3 = dz.sum(axis=0)
+    dh2 = (dzb @ W3) * (h2 > 0)
+    gb2 = dh2.sum(axis=0)
+    dh2b = _bf16(dh2).astype(np.float64)
+    gW2 = dh2b.T @ h1
+    dh1 = (dh2b @ W2) * (h1 > 0)
+    gb1 = dh1.sum(axis=0)
+    gW1 = _bf16(dh1).astype(np.float64).T @ xb
+    return {"W1": gW1.ravel(), "b1": gb1, "W2": gW2.ravel(), "b2": gb2, "W3": gW3.ravel(),
+            "b3": gb3}
+
+
+BLOCKS = {"W1": slice(0, 256), "b1": slice(256, 288), "W2": slice(288, 1312),
+          "b2": slice(1312, 1344), "W3": slice(1344, 1632), "b3": slice(1632, 1641)}
+
+
+def test_gradient_blocks_match_the_rounded_reference(lib, ctx):
+    """Every parameter block of the kernel gradient (W1, b1, W2, b2, W3, b3)
+    within 1e-2 (relative 2-norm) of a reference that rounds to bf16 where
+    the kernels do; what is left is float32 accumulation order and the odd
+    bf16 tie that goes the other way."""
+    import torch
+    rs = np.random.default_rng(12)
+    P = _params(12, 0.3)
+    n = 777
+    X = rs.uniform(0, 1, size=(n, 8)).astype(np.float32)
+    Y = rs.dirichlet(np.ones(4), size=(n, 2)).reshape(n, 8).astype(np.float32)
+    Cc = (rs.random(n) < 0.5).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    grad = torch.zeros(oracle.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    ctx.mlp_loss_grad(_dev(P), _dev(X), _dev(Y), _dev(Cc), loss, grad)
+    g = grad.cpu().numpy().astype(np.float64)
+    ref = _rounded_reference_grad(P, X, Y, Cc.astype(np.float64))
+    for name, sl in BLOCKS.items():
+        r = ref[name]
+        rel = np.linalg.norm(g[sl] - r) / np.linalg.norm(r)
+        print(f"[mlp] gradient block {name}: rel {rel:.2e}", flush=True)
+        assert rel <= 1e-2, (name, rel)
 
 
 def test_kernel_formed_confidence_targets(lib, ctx):
@@ -123,7 +206,8 @@ def test_kernel_formed_confidence_targets(lib, ctx):
     z = out.cpu().numpy().astype(np.float64)
     soft = lambda a: np.exp(a - a.max(1, keepdims=True)) / np.exp(a - a.max(1, keepdims=True)).sum(1, keepdims=True)
     Yh = np.concatenate([soft(z[:, :4]), soft(z[:, 4:8])], axis=1)
-    cl, cr = (c.cpu().numpy() for c in learned.candidates(torch.from_numpy(X)))
+    # the oracle's candidates of eq. (20) on the left stencils X[:, 0..4]
+    cl = np.array([oracle.weno_candidates(x[:5]) for x in X.astype(np.float64)])
     # move 0.1 of weight between the first two left candidates on samples
     # where they differ by more than 0.2 (value error > 0.02), none elsewhere
     move = (rs.random(n) < 0.5) & (np.abs(cl[:, 0] - cl[:, 1]) > 0.2)
@@ -240,20 +324,44 @@ def test_training_and_learned_weights_in_the_solver(lib, ctx):
     print(f"[mlp] eval {ev}", flush=True)
     packed = torch.zeros(lib.MLP_NPARAM, dtype=torch.int16, device="cuda")
     ctx.mlp_pack(P, packed)
+    # the same network before training (its initial parameters): what the
+    # training gains
+    packed0 = torch.zeros(lib.MLP_NPARAM, dtype=torch.int16, device="cuda")
+    ctx.mlp_pack(_dev(learned.init_params(seed=1707)), packed0)
     p = wl.sod_gas_liquid(200)
     g = lib.make_grid(p.n, p.dx, 0, 0)
+    og = oracle.make_grid(p.n, p.dx, 0, 0)
+    ref, _, _, _ = oracle.run(p.U, og, oracle.make_opts(mood=True), t_end=p.t_end)
+    W = oracle.exact_sample(p.extra["WL"], p.extra["WR"], (p.extra["x"] - 0.7) / p.t_end)
     res = {}
     for name, o in (("fp32", lib.make_opts(precision=lib.FP32, mood=True)),
                     ("mlp", lib.make_opts(precision=lib.FP32, weights=lib.W_MLP, mood=True,
-                                          mlp_params=packed))):
+                                          mlp_params=packed)),
+                    ("untrained", lib.make_opts(precision=lib.FP32, weights=lib.W_MLP, mood=True,
+                                                mlp_params=packed0))):
         U = _dev(p.U)
         st = lib.new_stats()
-        lib.Solver(g, o, ctx).run(U, t_end=p.t_end, stats=st)
+        _, _, k = lib.Solver(g, o, ctx).run(U, t_end=p.t_end, stats=st)
         s = lib.read_stats(st)
-        print(f"[mlp] shock tube {name}: status {s.status} mood o3 {s.o3[0]} o1 {s.o1[0]} "
-              f"fallbacks {s.mlp_fallback[0]}", flush=True)
+        got = U.cpu().numpy()
+        # learned face-fields evaluated: 201 faces x 3 non-material fields x 3 stages per step
+        evals = 201 * 3 * 3 * k
+        res[name] = {"status": s.status, "o3": s.o3[0], "o1": s.o1[0],
+                     "fallback_rate": s.mlp_fallback[0] / evals,
+                     "l1_exact": np.abs(got[0] - W[:, 0]).mean() / 1000.0,
+                     "l1_oracle": np.abs(got[0] - ref[0]).sum() / np.abs(ref[0]).sum()}
+        print(f"[mlp] shock tube {name}: {res[name]}", flush=True)
         assert s.status == 0
-        W = oracle.exact_sample(p.extra["WL"], p.extra["WR"], (p.extra["x"] - 0.7) / p.t_end)
-        res[name] = (np.abs(U.cpu().numpy()[0] - W[:, 0]).mean() / 1000.0, s.mlp_fallback[0])
-    print(f"[mlp] shock tube L1(rho)/1000: {res}", flush=True)
-    assert res["mlp"][0] < 2.0 * res["fp32"][0]
+    fp, ml, un = res["fp32"], res["mlp"], res["untrained"]
+    print(f"[mlp] learned/plain error against the exact solution {ml['l1_exact'] / fp['l1_exact']:.3f}; "
+          f"network weights used on {1 - ml['fallback_rate']:.3f} of the face-fields after "
+          f"training, {1 - un['fallback_rate']:.3f} before", flush=True)
+    # stated bounds of the learned form on this tube: within 2 % (relative
+    # L1 of rho) of the FP64 oracle's run, within 30 % of the plain FP32
+    # form's error against the exact solution, the network's own weights
+    # kept on at least half of the face-fields; and training is what gets
+    # it there (the untrained network falls back far more often)
+    assert ml["l1_oracle"] < 2e-2
+    assert ml["l1_exact"] < 1.3 * fp["l1_exact"]
+    assert ml["fallback_rate"] < 0.5
+    assert ml["fallback_rate"] < un["fallback_rate"]
