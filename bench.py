@@ -74,12 +74,14 @@ VALU_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 STAGE_SOURCES = ("face.hpp", "sweep.hpp", "kernels.hip", "stage2d.hip")
-COUNTERS_FILE = os.path.join(HERE, "profiles", "sweep_2d_shock_bubble_1024x512_counters.md")
+COUNTERS_FILE = os.path.join(HERE, "profiles", "stage_2d_shock_bubble_1024x512_counters.md")
+COUNTERS_3D = os.path.join(HERE, "profiles", "sweep_3d_shock_droplet_256_counters.md")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the stage-kernel sources have changed since it was taken."""
+def measured_traffic(kernel, counters_file=None):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (default: the 2D benchmark's), or None when the stage-kernel sources
+    have changed since it was taken."""
     import hashlib
     import re
     h = hashlib.sha256()
@@ -87,7 +89,7 @@ def measured_traffic(kernel):
         with open(os.path.join(HERE, "paper_1707_00592_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     try:
-        text = open(COUNTERS_FILE).read()
+        text = open(counters_file or COUNTERS_FILE).read()
     except OSError:
         return None
     m = re.search(r"stage-kernel sources: ([0-9a-f]{16})", text)
@@ -114,12 +116,18 @@ def parse():
                          "(for profiling developed states; 0 for the benchmark)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--extras", default="mlp,accuracy,study,paper2d,3d,batch",
-                    help="other workloads to report: mlp (learned weights, trained here), "
+    ap.add_argument("--extras", default="config1,mlp,accuracy,study,paper2d,3d,batch",
+                    help="other workloads to report: config1 (the 200-cell gas-liquid shock "
+                         "tube), mlp (learned weights, trained here), "
                          "accuracy (every form against a 2x finer FP64 run), study (basic "
                          "against modified weights, 1D convergence), paper2d (the paper's 2D "
                          "cylinder, droplet and bubble cases at full size), 3d (256^3 "
                          "shock-droplet), batch (4096 uneven tubes); empty for none")
+    ap.add_argument("--steps-3d", type=int, default=200,
+                    help="steps of the 3D shock-droplet workload (its configuration: 200)")
+    ap.add_argument("--t-end-steps", type=int, default=1000,
+                    help="the learned-weights workload runs to the time the 1024x512 FP64 run "
+                         "reaches in this many steps (its configuration: 1000)")
     return ap.parse_args()
 
 
@@ -144,24 +152,44 @@ def run_steps(isweno, ctx, p, U0, opts, steps, warmup, torch):
 
 
 def extra_3d(isweno, workloads, ctx, torch, steps=200):
-    """3D shock-droplet 256^3, FP32 reconstruction with FP64 recovery, vs the
-    FP64 path on the same steps; HBM roofline from algorithmic bytes."""
+    """3D shock-droplet 256^3, FP32 reconstruction with FP64 recovery, next
+    to the FP64 path on the same steps: throughput, per-kernel times over
+    every step (a second, directly launched pass), the HBM roofline from
+    algorithmic bytes and, while the stage sources match the committed
+    counter summary, the measured HBM bytes of each sweep."""
     p = workloads.shock_droplet_3d(256)
     U0 = torch.from_numpy(p.U).to("cuda")
     del p.U
     out = {"workload": "3D shock-droplet 256^3, MOOD on, CFL 0.5", "steps": steps}
     res = {}
     for name, prec in (("fp32", isweno.FP32), ("fp64", isweno.FP64)):
-        U, el, st = run_steps(isweno, ctx, p, U0, isweno.make_opts(precision=prec), steps, 2,
-                              torch)
+        U, el, kern, st, _ = run_form(isweno, ctx, p, U0, isweno.make_opts(precision=prec),
+                                      steps, 2, torch)
         v = p.ncells * 3 * steps / el
         bw = v * BYTES_PER_CELL_STAGE(3) / 1e9
         res[name] = U
+        for k, rec in kern.items():
+            t = measured_traffic(f"{name} {k}", COUNTERS_3D)
+            if t is not None:
+                rec["traffic_bytes_per_launch"] = t
+                rec["hbm_at_traffic_gbs"] = round(t / (rec["avg_ms"] * 1e-3) / 1e9, 1)
         out[name] = {"value": v, "unit": "cell-updates/s per RK stage", "status": st.status,
+                     "kernels": kern,
                      "hbm_roofline": {"bound": "hbm", "achieved": round(bw, 1),
                                       "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                                       "frac": round(bw / PEAK["hbm_gbs"], 4),
                                       "bytes_per_cell_stage": round(BYTES_PER_CELL_STAGE(3), 1)}}
+        traffic = [r.get("traffic_bytes_per_launch") for k, r in kern.items()
+                   if k.startswith("sweep")]
+        if traffic and all(t is not None for t in traffic):
+            # measured bytes of a stage (x, y and z sweeps) against the
+            # algorithmic bytes of a stage
+            per_stage = sum(traffic)
+            out[name]["hbm_roofline"]["traffic"] = per_stage
+            out[name]["hbm_roofline"]["traffic_over_algorithmic"] = round(
+                per_stage / (p.ncells * BYTES_PER_CELL_STAGE(3)), 3)
+        else:
+            out[name]["hbm_roofline"]["traffic"] = None
     out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
     out["fp32"]["l1_rel_rho_vs_fp64"] = l1_rel(res["fp32"][0], res["fp64"][0])
     del res, U0
@@ -245,11 +273,25 @@ def extra_batch(isweno, workloads, ctx, torch, steps=100):
     return out
 
 
-def extra_mlp(isweno, workloads, ctx, torch, steps=300):
+def config2_t_end(isweno, workloads, ctx, torch, nsteps=1000):
+    """The time the 1024 x 512 shock-bubble (FP64, CFL 0.5) reaches in its
+    configured 1000 steps: the final time of the workload at every
+    resolution and form."""
+    p = workloads.shock_bubble_2d(1024, 512)
+    g = isweno.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    U = torch.from_numpy(p.U).to("cuda")
+    _, t_end, _ = isweno.Solver(g, isweno.make_opts(), ctx).run(U, nsteps=nsteps, t_end=1.0)
+    return t_end
+
+
+def extra_mlp(isweno, workloads, ctx, torch, t_end):
     """Learned weights: trained on the GPU on faces of plain runs of the
     gas-liquid shock tube and the 3D shock-droplet (at 96^3), then run on
-    the 2D shock-bubble at 2048 x 1024 next to the FP64 and FP32 forms.
-    Returns (report, packed network)."""
+    the 2D shock-bubble at 2048 x 1024 to the final time of the 1000-step
+    1024 x 512 workload (t_end), next to the FP64 and FP32 forms.  Each form
+    runs twice from the initial state: once to t_end exactly (the last step
+    clipped; the state compared), once timed over the same number of steps
+    as HIP-graph replays.  Returns (report, packed network)."""
     from paper_1707_00592_amd import learned
     t0 = time.perf_counter()
     opts64 = isweno.make_opts()
@@ -265,31 +307,59 @@ def extra_mlp(isweno, workloads, ctx, torch, steps=300):
     packed = torch.zeros(isweno.MLP_NPARAM, dtype=torch.int16, device="cuda")
     ctx.mlp_pack(P, packed)
     p2 = workloads.shock_bubble_2d(2048, 1024)
+    g2 = isweno.make_grid(p2.n, p2.dx, p2.bc_lo, p2.bc_hi)
     U2 = torch.from_numpy(p2.U).to("cuda")
     forms = {"fp64": isweno.make_opts(),
              "fp32": isweno.make_opts(precision=isweno.FP32),
              "mlp": learned_opts(isweno, packed)}
-    out = {"workload": "2D shock-bubble 2048x1024, MOOD on, CFL 0.5", "steps": steps}
+    out = {"workload": "2D shock-bubble 2048x1024, MOOD on, CFL 0.5", "t_end": t_end}
     res = {}
     for name, o in forms.items():
-        U, el, kern, st, _ = run_form(isweno, ctx, p2, U2, o, steps, 5, torch, 20)
+        U = U2.clone()
+        st = isweno.new_stats()
+        _, t, k = isweno.Solver(g2, o, ctx).run(U, t_end=t_end, stats=st)
+        st = isweno.read_stats(st)
         res[name] = U
-        # learned face-fields (the four non-material fields) evaluated over
-        # both warmups, the timed and the kernel-timing steps
-        faces = sum(p2.ncells // p2.n[d] * (p2.n[d] + 1) for d in range(2)) * 4 * 3 * (steps + 30)
-        out[name] = {"value": p2.ncells * 3 * steps / el, "unit": "cell-updates/s per RK stage",
-                     "status": st.status, "kernels": kern}
+        # learned face-fields (the four non-material fields) of those k steps
+        faces = sum(p2.ncells // p2.n[d] * (p2.n[d] + 1) for d in range(2)) * 4 * 3 * k
+        _, el, kern, _, _ = run_form(isweno, ctx, p2, U2, o, k, 0, torch, 20)
+        out[name] = {"value": p2.ncells * 3 * k / el, "unit": "cell-updates/s per RK stage",
+                     "steps": k, "status": st.status, "kernels": kern,
+                     "mood": {"o3": list(st.o3[:2]), "o1": list(st.o1[:2])}}
         if name == "mlp":
             out[name]["fallback_rate"] = float(sum(st.mlp_fallback[:2])) / faces
+    pref = pressure(res["fp64"])
     for name in ("fp32", "mlp"):
         out[name]["speedup_vs_fp64"] = out[name]["value"] / out["fp64"]["value"]
         out[name]["l1_rel_rho_vs_fp64"] = l1_rel(res[name][0], res["fp64"][0])
-        out[name]["l1_rel_E_vs_fp64"] = l1_rel(res[name][3], res["fp64"][3])
+        out[name]["l1_rel_p_vs_fp64"] = l1_rel(pressure(res[name]), pref)
+    out["mlp"]["speedup_vs_fp32"] = out["mlp"]["value"] / out["fp32"]["value"]
+    out["note"] = ("the FP64 path equals the oracle bit for bit (parity tests), so its state is "
+                   "the FP64 reference of the L1 figures")
     out["training"] = {"samples": int(Xs.shape[0]), "adam_steps": 3000,
                        "seconds": round(train_s, 1), "loss": hist, **ev}
     del res, U2
     torch.cuda.empty_cache()
     return out, packed
+
+
+def extra_config1(isweno, workloads, ctx, torch):
+    """The 200-cell gas-liquid shock tube (MOOD off, as in Sec. 5) to
+    t = 2.4e-4 s: launch-bound at this size; timed as graph replays of the
+    step count the run to t_end takes."""
+    p = workloads.sod_gas_liquid(200)
+    g = isweno.make_grid(p.n, p.dx, p.bc_lo, p.bc_hi)
+    out = {"workload": "1D gas-liquid shock tube, 200 cells, t_end 2.4e-4 s"}
+    for name, prec in (("fp64", isweno.FP64), ("fp32", isweno.FP32)):
+        o = isweno.make_opts(precision=prec, mood=False)
+        U = torch.from_numpy(p.U).to("cuda")
+        _, t, k = isweno.Solver(g, o, ctx).run(U, t_end=p.t_end)
+        U0 = torch.from_numpy(p.U).to("cuda")
+        _, el, _, st, _ = run_form(isweno, ctx, p, U0, o, k, 5, torch, 5)
+        out[name] = {"steps": k, "value": p.ncells * 3 * k / el,
+                     "unit": "cell-updates/s per RK stage", "ms_per_step": el / k * 1e3,
+                     "status": st.status}
+    return out
 
 
 def learned_opts(isweno, packed):
@@ -470,7 +540,10 @@ def roofline(kern, p, precision, with_traffic=False):
     sec = k["avg_ms"] * 1e-3
     achieved = flops / sec / 1e12
     peak = PEAK["f64_valu_tflops"] if precision == "f64" else PEAK["f32_valu_tflops"]
-    traffic = measured_traffic(name) if with_traffic else None
+    # the committed counters cover the timed window from the initial state
+    traffic = None
+    if with_traffic:
+        traffic = measured_traffic(name if precision == "f64" else "fp32 " + name)
     out = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": peak,
            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
            "peak_no_fma": round(VALU_OPS_PEAK_T, 1),
@@ -520,6 +593,13 @@ def cpu_baseline(p, seconds):
             "per_core_sample": f"first {steps1} RK3 steps on one thread ({el1:.1f} s)"}
 
 
+def progress(msg, t0=None):
+    """One line on stderr as each part of the run ends (the JSON line is
+    the only output on stdout)."""
+    tail = "" if t0 is None else f" ({time.perf_counter() - t0:.1f} s)"
+    print(f"bench.py: {msg}{tail}", file=sys.stderr, flush=True)
+
+
 def rel_l1(a, b):
     return float((a - b).abs().sum() / b.abs().sum())
 
@@ -547,11 +627,13 @@ def main():
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
     for f in forms:
+        t0 = time.perf_counter()
         prec = isweno.FP32 if f == "fp32" else isweno.FP64
         opts = isweno.make_opts(precision=prec, mood=True, cfl=0.5)
         U, el, kern, st, direct = run_form(isweno, ctx, p, U0, opts, args.steps, args.warmup,
                                            torch)
         results[f] = {"U": U, "elapsed": el, "kern": kern, "stats": st, "direct": direct}
+        progress(f"timed steps, {f}", t0)
     base = results["fp64"]
     cells_stages = p.ncells * 3 * args.steps
     value = cells_stages / base["elapsed"]
@@ -592,7 +674,9 @@ def main():
     for f in (forms if nfull > 0 else []):
         prec = isweno.FP32 if f == "fp32" else isweno.FP64
         o = isweno.make_opts(precision=prec, mood=True, cfl=0.5)
+        t0 = time.perf_counter()
         Uf, el, kern, st, same = full_run(isweno, ctx, p, U0, o, nfull, torch)
+        progress(f"full run, {f}", t0)
         full_U[f] = Uf
         full[f] = {"value": p.ncells * 3 * nfull / el,
                    "kernels": kern,
@@ -620,22 +704,40 @@ def main():
                         "l1_rel_rho_vs_fp64": rel_l1(r["U"][0], rho64),
                         "l1_rel_E_vs_fp64": rel_l1(r["U"][3], base["U"][3]),
                         "status": r["stats"].status,
-                        "roofline": roofline(r["kern"], p, "f32")}
+                        "roofline": roofline(r["kern"], p, "f32", with_traffic=(f == "fp32"))}
     extras = [e.strip() for e in args.extras.split(",") if e.strip()]
     out["forms"] = forms_out
     other = {}
     packed = None
-    if "mlp" in extras:
+    if "config1" in extras:
+        t0 = time.perf_counter()
         try:
-            other["learned_weights"], packed = extra_mlp(isweno, workloads, ctx, torch)
+            other["gas_liquid_tube_200"] = extra_config1(isweno, workloads, ctx, torch)
+        except Exception as e:  # report, keep the contract line
+            other["gas_liquid_tube_200"] = {"error": repr(e)}
+        progress("config1", t0)
+    if "mlp" in extras:
+        t0 = time.perf_counter()
+        try:
+            t_end = config2_t_end(isweno, workloads, ctx, torch, args.t_end_steps)
+            other["learned_weights"], packed = extra_mlp(isweno, workloads, ctx, torch, t_end)
             o = learned_opts(isweno, packed)
-            _, el, _, st, _ = run_form(isweno, ctx, p, U0, o, min(args.steps, 300), 5, torch, 5)
-            forms_out["mlp"] = {"value": cells_stages / args.steps * min(args.steps, 300) / el,
-                                "status": st.status}
-            forms_out["mlp"]["speedup_vs_fp64"] = forms_out["mlp"]["value"] / value
+            nfull = max(args.full_steps, 1)
+            Uf, el, kern, st, _ = full_run(isweno, ctx, p, U0, o, nfull, torch)
+            faces = sum(p.ncells // p.n[d] * (p.n[d] + 1) for d in range(2)) * 4 * 3 * nfull
+            forms_out["mlp"] = {"value": p.ncells * 3 * nfull / el, "steps": nfull,
+                                "note": f"{nfull} steps from the initial state (the configured "
+                                        "run), as config_full_run",
+                                "status": st.status, "kernels": kern,
+                                "fallback_rate": float(sum(st.mlp_fallback[:2])) / faces}
+            forms_out["mlp"]["speedup_vs_fp64"] = forms_out["mlp"]["value"] / (
+                out["config_full_run"]["fp64"]["value"] if "config_full_run" in out else value)
+            del Uf
         except Exception as e:  # report, keep the contract line
             other["learned_weights"] = {"error": repr(e)}
+        progress("mlp", t0)
     if "accuracy" in extras:
+        t0 = time.perf_counter()
         try:
             fo = {"fp64": isweno.make_opts(), "fp32": isweno.make_opts(precision=isweno.FP32)}
             vals = {"fp64": value}
@@ -647,31 +749,42 @@ def main():
             other["equal_l1_1024x512"] = equal_l1(isweno, workloads, ctx, torch, fo, vals)
         except Exception as e:
             other["equal_l1_1024x512"] = {"error": repr(e)}
+        progress("accuracy", t0)
     if "study" in extras:
+        t0 = time.perf_counter()
         try:
             from paper_1707_00592_amd import studies
             other["weights_study_1d"] = studies.weights_study(ctx)
         except Exception as e:
             other["weights_study_1d"] = {"error": repr(e)}
+        progress("study", t0)
     if "paper2d" in extras:
+        t0 = time.perf_counter()
         try:
             other["paper_2d"] = extra_paper2d(isweno, workloads, ctx, torch)
         except Exception as e:
             other["paper_2d"] = {"error": repr(e)}
+        progress("paper2d", t0)
     if "3d" in extras:
+        t0 = time.perf_counter()
         try:
-            other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch)
+            other["shock_droplet_3d"] = extra_3d(isweno, workloads, ctx, torch, args.steps_3d)
         except Exception as e:
             other["shock_droplet_3d"] = {"error": repr(e)}
+        progress("3d", t0)
     if "batch" in extras:
+        t0 = time.perf_counter()
         try:
             other["batch_riemann"] = extra_batch(isweno, workloads, ctx, torch)
         except Exception as e:
             other["batch_riemann"] = {"error": repr(e)}
+        progress("batch", t0)
     if other:
         out["other_workloads"] = other
     if not args.no_cpu:
+        t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        progress("cpu baseline", t0)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per
         # dispatch scale the counters of the stage kernels to bytes
