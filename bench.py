@@ -73,7 +73,7 @@ PEAK = {"f64_valu_tflops": 78.6, "f32_valu_tflops": 157.3, "hbm_gbs": 8000.0}
 VALU_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STAGE_SOURCES = ("face.hpp", "sweep.hpp", "kernels.hip", "stage2d.hip")
+STAGE_SOURCES = ("face.hpp", "sweep.hpp", "sweep_kernels.hpp", "kernels.hip", "stage2d.hip")
 COUNTERS_FILE = os.path.join(HERE, "profiles", "stage_2d_shock_bubble_1024x512_counters.md")
 COUNTERS_3D = os.path.join(HERE, "profiles", "sweep_3d_shock_droplet_256_counters.md")
 
@@ -108,7 +108,8 @@ def parse():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--forms", default="fp64,fp32,cutoff",
+                    help="forms of the main workload: fp64 (the headline), fp32, cutoff")
     ap.add_argument("--full-steps", type=int, default=1000,
                     help="steps of the full-run report (the workload as configured); 0 skips it")
     ap.add_argument("--skip", type=int, default=0,
@@ -593,6 +594,15 @@ def cpu_baseline(p, seconds):
             "per_core_sample": f"first {steps1} RK3 steps on one thread ({el1:.1f} s)"}
 
 
+def form_opts(isweno, f):
+    """Options of a named form of the main workload: fp64 (the method), fp32
+    (float reconstruction and flux), cutoff (FP64 with the targeted-ENO
+    cut-off weights)."""
+    prec = isweno.FP32 if f == "fp32" else isweno.FP64
+    w = isweno.W_CUTOFF if f == "cutoff" else isweno.W_MODIFIED
+    return isweno.make_opts(precision=prec, weights=w, mood=True, cfl=0.5)
+
+
 def progress(msg, t0=None):
     """One line on stderr as each part of the run ends (the JSON line is
     the only output on stdout)."""
@@ -628,8 +638,7 @@ def main():
     results = {}
     for f in forms:
         t0 = time.perf_counter()
-        prec = isweno.FP32 if f == "fp32" else isweno.FP64
-        opts = isweno.make_opts(precision=prec, mood=True, cfl=0.5)
+        opts = form_opts(isweno, f)
         U, el, kern, st, direct = run_form(isweno, ctx, p, U0, opts, args.steps, args.warmup,
                                            torch)
         results[f] = {"U": U, "elapsed": el, "kern": kern, "stats": st, "direct": direct}
@@ -672,25 +681,26 @@ def main():
             "steps"}
     full_U = {}
     for f in (forms if nfull > 0 else []):
-        prec = isweno.FP32 if f == "fp32" else isweno.FP64
-        o = isweno.make_opts(precision=prec, mood=True, cfl=0.5)
+        o = form_opts(isweno, f)
         t0 = time.perf_counter()
         Uf, el, kern, st, same = full_run(isweno, ctx, p, U0, o, nfull, torch)
         progress(f"full run, {f}", t0)
         full_U[f] = Uf
         full[f] = {"value": p.ncells * 3 * nfull / el,
                    "kernels": kern,
-                   "roofline": roofline(kern, p, "f32" if f == "fp32" else "f64"),
+                   "roofline": (roofline(kern, p, "f32" if f == "fp32" else "f64")
+                                if f != "cutoff" else None),
                    "mood": {"o3": list(st.o3[:2]), "o1": list(st.o1[:2]), "status": st.status},
                    "timing_pass_bitwise_equal": same}
         full[f]["ms_per_step"] = el / nfull * 1e3
         full[f]["hbm_frac_of_value"] = round(
             full[f]["value"] * BYTES_PER_CELL_STAGE(p.ndim) / 1e9 / PEAK["hbm_gbs"], 4)
-    if "fp32" in full_U:
-        full["fp32"]["speedup_vs_fp64"] = full["fp32"]["value"] / full["fp64"]["value"]
-        full["fp32"]["l1_rel_rho_vs_fp64"] = rel_l1(full_U["fp32"][0], full_U["fp64"][0])
-        full["fp32"]["l1_rel_p_vs_fp64"] = rel_l1(pressure(full_U["fp32"]),
-                                                  pressure(full_U["fp64"]))
+    for f in full_U:
+        if f == "fp64" or "fp64" not in full_U:
+            continue
+        full[f]["speedup_vs_fp64"] = full[f]["value"] / full["fp64"]["value"]
+        full[f]["l1_rel_rho_vs_fp64"] = rel_l1(full_U[f][0], full_U["fp64"][0])
+        full[f]["l1_rel_p_vs_fp64"] = rel_l1(pressure(full_U[f]), pressure(full_U["fp64"]))
     if nfull > 0:
         out["config_full_run"] = full
     del full_U
@@ -704,7 +714,11 @@ def main():
                         "l1_rel_rho_vs_fp64": rel_l1(r["U"][0], rho64),
                         "l1_rel_E_vs_fp64": rel_l1(r["U"][3], base["U"][3]),
                         "status": r["stats"].status,
-                        "roofline": roofline(r["kern"], p, "f32", with_traffic=(f == "fp32"))}
+                        "kernels": r["kern"]}
+        if f == "fp32":
+            # (the operation counts are those of the eq. (28) weights: no
+            # roofline line for the cut-off form)
+            forms_out[f]["roofline"] = roofline(r["kern"], p, "f32", with_traffic=True)
     extras = [e.strip() for e in args.extras.split(",") if e.strip()]
     out["forms"] = forms_out
     other = {}

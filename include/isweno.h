@@ -86,7 +86,7 @@ enum {
 enum {
   ISWENO_W_MODIFIED = 0, /* eq. (28), Sec. 3.3.2 (the paper's final form) */
   ISWENO_W_BASIC = 1,    /* eq. (21) with q = 1 */
-  ISWENO_W_MLP = 2       /* learned weights (isweno_mlp_*) for the
+  ISWENO_W_MLP = 2,      /* learned weights (isweno_mlp_*) for the
                             acoustic, entropy and shear fields, with the
                             eq. (28) weights as fallback (confidence below
                             the threshold, a face value outside the range
@@ -95,6 +95,17 @@ enum {
                             is redone with them before the MOOD cascade)
                             and for the material fields Gamma, Pi
                             throughout */
+  ISWENO_W_CUTOFF = 3    /* not in the paper: the targeted-ENO cut-off that
+                            its conclusions (Sec. 7) propose for lower
+                            dissipation in smooth regions, on the eq. (28)
+                            quantities.  Stencil k has the measure
+                            gamma_k = (alpha_k/d_k)^6; stencils whose share
+                            gamma_k / sum gamma is below C_T = 1e-5 get
+                            weight 0, the others d_k renormalised over the
+                            kept ones (exactly d_k when none is cut, i.e.
+                            the linear 5th-order scheme on resolved smooth
+                            data).  Order 3 of the MOOD cascade cuts among
+                            the two 2-point stencils. */
 };
 
 typedef struct {

@@ -25,7 +25,7 @@ SOURCES = ["oracle.c", "exact_riemann.c", "mlp_ref.c"]
 
 OK, ERR_ARG, ERR_NONPHYSICAL, ERR_VACUUM = 0, -1, -4, -5
 BC_TRANSMISSIVE, BC_PERIODIC, BC_REFLECTIVE = 0, 1, 2
-W_MODIFIED, W_BASIC = 0, 1
+W_MODIFIED, W_BASIC, W_CUTOFF = 0, 1, 3
 MLP_NI, MLP_H, MLP_NO = 8, 32, 9
 MLP_NPARAM = MLP_H * MLP_NI + MLP_H + MLP_H * MLP_H + MLP_H + MLP_NO * MLP_H + MLP_NO
 

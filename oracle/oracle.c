@@ -79,9 +79,62 @@ void or_weno_indicators(const double v[5], double ind[6]) {
 /* Optimal weights d_k of Sec. 3.3.1. */
 static const double OR_D[4] = {0.4, 0.2, 0.3, 0.1};
 
+/* Cut-off weights (OR_W_CUTOFF), the targeted-ENO optimisation that Sec. 7
+ * proposes for lower dissipation in smooth regions, applied to the
+ * weights of eq. (28).  Stencil k gets the targeted-ENO smoothness measure
+ *   gamma_k = (1 + r_k)^q,  q = OR_CUTOFF_Q,
+ * with r_k the ratio term of eq. (28) for that stencil (the product
+ * tau_5/(beta_k + eps) * tau_5/(beta_12 + eps) for the 2-point stencils,
+ * tau_5/(beta_k + eps) for the 3-point ones), so that 1 + r_k =
+ * alpha_k / d_k.  Its share chi_k = gamma_k / sum_s gamma_s is compared
+ * with C_T = OR_CUTOFF_CT: delta_k = 1 if chi_k >= C_T, else 0, and
+ *   omega_k = d_k delta_k / sum_s d_s delta_s.
+ * On data smooth enough that no stencil is cut this is exactly the linear
+ * 5th-order scheme; a stencil crossing a discontinuity gets weight zero.
+ * (On the single ratios of eq. (21) the cut-off would inherit that form's
+ * loss of order at critical points, where a 2-point indicator vanishes.)
+ * Order 3 of the MOOD cascade keeps the two 2-point stencils only (as
+ * d3 = d4 = 0 does for the other forms) and cuts among them.  Evaluation:
+ * gamma_k overflows for the pressure-like fields, so each 1 + r_k is first
+ * divided by the largest of them, t_k = g_k / g_max, and chi_k >= C_T is
+ * tested as t_k^6 >= C_T sum_s t_s^6 (the same inequality multiplied by
+ * g_max^-6), with t^6 formed as (t^2 t^2) t^2 and the sum in stencil order.
+ * The optimal weights are taken as 4, 2, 3, 1 over their kept sum (exact
+ * integers), so that an uncut stencil set gives omega_k = d_k to the last
+ * bit. */
+static void cutoff_weights(const double ind[6], double eps, int order,
+                           double omega[4]) {
+  static const double dint[4] = {4.0, 2.0, 3.0, 1.0};
+  const int ns = order == 3 ? 2 : 4;
+  const double tau5 = ind[5];
+  double g[4], p[4], gmax, psum, dsum;
+  int k, keep[4];
+  const double r12 = tau5 / (ind[4] + eps);
+  g[0] = 1.0 + (tau5 / (ind[0] + eps)) * r12;
+  g[1] = 1.0 + (tau5 / (ind[1] + eps)) * r12;
+  g[2] = 1.0 + tau5 / (ind[2] + eps);
+  g[3] = 1.0 + tau5 / (ind[3] + eps);
+  gmax = g[0];
+  for (k = 1; k < ns; k++)
+    if (g[k] > gmax) gmax = g[k];
+  psum = 0.0;
+  for (k = 0; k < ns; k++) {
+    const double t = g[k] / gmax;
+    const double t2 = t * t;
+    p[k] = (t2 * t2) * t2;
+    psum += p[k];
+  }
+  dsum = 0.0;
+  for (k = 0; k < 4; k++) {
+    keep[k] = k < ns && p[k] >= OR_CUTOFF_CT * psum;
+    if (keep[k]) dsum += dint[k];
+  }
+  for (k = 0; k < 4; k++) omega[k] = keep[k] ? dint[k] / dsum : 0.0;
+}
+
 /* Nonlinear weights.  Basic form: eq. (21) with q = 1.  Modified form:
  * eq. (28), where each alpha line carries its own d_k (the printed "d_k"
- * on every line is read as d_1..d_4 in turn).  Order 3 sets d3 = d4 = 0
+ * on every line is read as d_1..d_4 in turn).  Cut-off form: above.  Order 3 sets d3 = d4 = 0
  * (end of Sec. 3.3.1), i.e. only the two 2-point stencils remain. */
 void or_weno_weights(const double v[5], int weights, double eps, int order,
                      double omega[4]) {
@@ -89,6 +142,10 @@ void or_weno_weights(const double v[5], int weights, double eps, int order,
   int k;
   or_weno_indicators(v, ind);
   const double tau5 = ind[5];
+  if (weights == OR_W_CUTOFF) {
+    cutoff_weights(ind, eps, order, omega);
+    return;
+  }
   if (weights == OR_W_BASIC) {
     for (k = 0; k < 4; k++) alpha[k] = OR_D[k] * (1.0 + tau5 / (ind[k] + eps));
   } else {

@@ -42,6 +42,13 @@ extern "C" {
 
 #define OR_W_MODIFIED 0 /* Sec. 3.3.2, eq. (28) */
 #define OR_W_BASIC 1    /* Sec. 3.3.1, eq. (21) with q = 1 */
+/* Cut-off of the eq. (28) weights in the manner of the targeted ENO schemes
+ * that the conclusions (Sec. 7) name as the next step: stencils whose share
+ * of the smoothness measure is below OR_CUTOFF_CT are dropped, the others
+ * take the optimal weights.  Not part of the paper's scheme. */
+#define OR_W_CUTOFF 3
+#define OR_CUTOFF_CT 1e-5 /* C_T of the 5th-order targeted ENO scheme */
+#define OR_CUTOFF_Q 6     /* exponent q of its smoothness measure */
 
 #define OR_MAXNC 7
 
@@ -53,7 +60,7 @@ typedef struct {
 } or_grid;
 
 typedef struct {
-  int weights; /* OR_W_MODIFIED or OR_W_BASIC */
+  int weights; /* OR_W_MODIFIED, OR_W_BASIC or OR_W_CUTOFF */
   int mood;    /* 1: MOOD-type positivity cascade of Sec. 3.4 */
   double eps;  /* epsilon of the weights, eqs. (21), (28) */
   double cfl;  /* Courant number for the time step */

@@ -20,7 +20,7 @@ LIB = BUILD / "libisweno.so"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "stage2d.hip", "batch.hip", "mlp.hip", "api.hip"]
+SOURCES = ["kernels.hip", "sweep_cut.hip", "stage2d.hip", "batch.hip", "mlp.hip", "api.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

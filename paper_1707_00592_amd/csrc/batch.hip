@@ -48,7 +48,7 @@ struct Lds1 {
   }
 };
 
-template <typename T, int TL, int MODE>
+template <typename T, int TL, int MODE, bool CUT>
 __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
   constexpr int NC = 5, NP = TL + 6, NF = TL + 1, NTHR = TL + 1;
   __shared__ double sq[NC * NP];
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       st.cstride = NP;
       double F[NC], us;
       int n3, n1, nf;
-      face_flux<T, 1, 0>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nf);
+      face_flux<T, 1, 0>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1, nf);
       if (j < len || l0 + j == n) {  // count each face of a problem once
         my3 += n3;
         my1 += n1;
@@ -169,15 +169,26 @@ __global__ __launch_bounds__(256) void batch_dt_kernel(const double* U, int64_t 
   }
 }
 
+template <typename T, int TL, bool CUT>
+static hipError_t launch_stage_c(const BatchArgs& a, int mode, int blocks, hipStream_t s) {
+  if (mode == OUT_RK1)
+    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK1, CUT>), dim3(blocks), dim3(TL + 1), 0,
+                       s, a);
+  else if (mode == OUT_RK2)
+    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK2, CUT>), dim3(blocks), dim3(TL + 1), 0,
+                       s, a);
+  else
+    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK3, CUT>), dim3(blocks), dim3(TL + 1), 0,
+                       s, a);
+  return hipGetLastError();
+}
+
+// the cut-off weights in kernels of their own (register allocation of the
+// other forms unchanged)
 template <typename T, int TL>
 static hipError_t launch_stage_tl(const BatchArgs& a, int mode, int blocks, hipStream_t s) {
-  if (mode == OUT_RK1)
-    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK1>), dim3(blocks), dim3(TL + 1), 0, s, a);
-  else if (mode == OUT_RK2)
-    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK2>), dim3(blocks), dim3(TL + 1), 0, s, a);
-  else
-    hipLaunchKernelGGL((batch_stage_kernel<T, TL, OUT_RK3>), dim3(blocks), dim3(TL + 1), 0, s, a);
-  return hipGetLastError();
+  return a.weights == W_CUTOFF ? launch_stage_c<T, TL, true>(a, mode, blocks, s)
+                               : launch_stage_c<T, TL, false>(a, mode, blocks, s);
 }
 
 template <typename T>
@@ -266,7 +277,7 @@ static int build_table(isweno_batch_plan* p, int tl) {
 static int check_batch_opts(const isweno_opts* o) {
   if (!o || o->reserved != 0 || o->reserved2 != 0) return ISWENO_ERR_ARG;
   if (o->precision != ISWENO_FP64 && o->precision != ISWENO_FP32) return ISWENO_ERR_ARG;
-  if (o->weights < 0 || o->weights > 2 || (o->mood != 0 && o->mood != 1)) return ISWENO_ERR_ARG;
+  if (o->weights < 0 || o->weights > 3 || (o->mood != 0 && o->mood != 1)) return ISWENO_ERR_ARG;
   if (!(o->eps >= 0.0)) return ISWENO_ERR_ARG;
   if (o->weights == ISWENO_W_MLP) return ISWENO_ERR_UNSUPPORTED;
   return ISWENO_OK;

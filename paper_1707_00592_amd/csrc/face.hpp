@@ -24,7 +24,10 @@ namespace isw {
 #define ISW_D4 0.1
 #define ISW_K13 (13.0 / 12.0)
 
-enum { W_MODIFIED = 0, W_BASIC = 1, W_MLP = 2 };
+enum { W_MODIFIED = 0, W_BASIC = 1, W_MLP = 2, W_CUTOFF = 3 };
+
+// Cut-off weights: the targeted-ENO threshold C_T of the 5th-order scheme.
+#define ISW_CT 1e-5
 
 template <typename T>
 __device__ __forceinline__ T dmin(T a, T b) { return a < b ? a : b; }
@@ -317,6 +320,126 @@ __device__ __forceinline__ float weno_f32(float a, float b, float c, float d,
   return c + s * ((a1 * C1 + a2 * C2 + a3 * C3 + a4 * C4) * inv);
 }
 
+// ---------------------------------------------------------------------------
+// Cut-off weights (W_CUTOFF): the targeted-ENO optimisation that the
+// conclusions (Sec. 7) propose for lower dissipation in smooth regions,
+// applied to the eq. (28) weights.  Each stencil's measure is
+// gamma_k = (alpha_k / d_k)^6 (alpha_k of eq. (28)); a stencil whose share
+// gamma_k / sum(gamma) is below C_T gets weight zero and the others the
+// optimal weights renormalised, d_k / sum(kept d).  The share test is taken
+// on t_k = (alpha_k/d_k) / max_s(alpha_s/d_s), as t_k^6 >= C_T sum t_s^6
+// (no overflow), and the renormalised weights as 4, 2, 3, 1 over their kept
+// sum, so that a stencil set with nothing cut gives d_k exactly.  Order 3
+// cuts among the two 2-point stencils.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cut_share_f64(double g, double gm) {
+  const double t = g / gm;
+  const double t2 = t * t;
+  return (t2 * t2) * t2;
+}
+
+// omega of every set of kept stencils (bit k-1 of the index: stencil k):
+// 4, 2, 3, 1 over the kept sum, divided (correctly rounded) at compile time.
+struct CutWeights {
+  double w[16][4];
+};
+constexpr CutWeights make_cut_weights() {
+  CutWeights t{};
+  const double dk[4] = {4.0, 2.0, 3.0, 1.0};
+  for (int m = 0; m < 16; m++) {
+    double ds = 0.0;
+    for (int k = 0; k < 4; k++)
+      if (m >> k & 1) ds += dk[k];
+    for (int k = 0; k < 4; k++) t.w[m][k] = (m >> k & 1) ? dk[k] / ds : 0.0;
+  }
+  return t;
+}
+__constant__ CutWeights kCutWeights = make_cut_weights();
+
+__device__ __forceinline__ double weno_f64_cutoff(double a, double b, double c, double d,
+                                                  double e, double eps, bool order3,
+                                                  int& nlin) {
+  int mask = 15;
+  if (eps > 0.0 && tau5<double>(a, b, c, d, e) == 0.0) {
+    // every ratio is zero: no stencil is cut
+    nlin++;
+  } else {
+    const Ind<double> s = indicators<double>(a, b, c, d, e);
+    const double r12 = s.tau / (s.b12 + eps);
+    const double g1 = 1.0 + (s.tau / (s.b1 + eps)) * r12;
+    const double g2 = 1.0 + (s.tau / (s.b2 + eps)) * r12;
+    double gm = g1;
+    if (g2 > gm) gm = g2;
+    if (order3) {
+      const double p1 = cut_share_f64(g1, gm), p2 = cut_share_f64(g2, gm);
+      const double th = ISW_CT * (p1 + p2);
+      mask = (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0);
+    } else {
+      const double g3 = 1.0 + s.tau / (s.b3 + eps);
+      const double g4 = 1.0 + s.tau / (s.b4 + eps);
+      if (g3 > gm) gm = g3;
+      if (g4 > gm) gm = g4;
+      const double p1 = cut_share_f64(g1, gm), p2 = cut_share_f64(g2, gm),
+                   p3 = cut_share_f64(g3, gm), p4 = cut_share_f64(g4, gm);
+      const double th = ISW_CT * (((p1 + p2) + p3) + p4);
+      mask = (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0) | (p3 >= th ? 4 : 0) | (p4 >= th ? 8 : 0);
+    }
+  }
+  if (order3) mask &= 3;
+  const double* w = kCutWeights.w[mask];
+  const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+  const double c2 = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+  if (order3) return w[0] * c1 + w[1] * c2;
+  const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+  const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+  return ((w[0] * c1 + w[1] * c2) + w[2] * c3) + w[3] * c4;
+}
+
+// The same cut-off in the float form: the stencil shifted and scaled as in
+// weno_f32, ratios clamped at 1e30, hardware reciprocals.
+__device__ __forceinline__ float weno_f32_cutoff(float a, float b, float c, float d, float e,
+                                                 float eps, bool order3, int& nshort) {
+  const float s = fmaxf(fmaxf(fmaxf(fabsf(a - c), fabsf(b - c)), fabsf(d - c)),
+                        fabsf(e - c));
+  if (!(s > 1e-30f)) {
+    nshort++;
+    return c;
+  }
+  const float is = __builtin_amdgcn_rcpf(s);
+  const float A = (a - c) * is, B = (b - c) * is, D = (d - c) * is,
+              E = (e - c) * is;
+  const Ind<float> r = indicators<float>(A, B, 0.0f, D, E);
+  const float es = fmaxf(eps * is * is, 1e-30f);
+  const float r12 = r.tau * __builtin_amdgcn_rcpf(r.b12 + es);
+  const float g1 = 1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b1 + es) * r12, 1e30f);
+  const float g2 = 1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b2 + es) * r12, 1e30f);
+  const float C1 = 0.5f * D;
+  const float C2 = -0.5f * B;
+  auto share = [](float g, float rg) {
+    const float t = g * rg;
+    const float t2 = t * t;
+    return (t2 * t2) * t2;
+  };
+  if (order3) {
+    const float rg = __builtin_amdgcn_rcpf(fmaxf(g1, g2));
+    const float p1 = share(g1, rg), p2 = share(g2, rg);
+    const float th = float(ISW_CT) * (p1 + p2);
+    const float k1 = p1 >= th ? 4.0f : 0.0f, k2 = p2 >= th ? 2.0f : 0.0f;
+    return c + s * ((k1 * C1 + k2 * C2) * __builtin_amdgcn_rcpf(k1 + k2));
+  }
+  const float g3 = 1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b3 + es), 1e30f);
+  const float g4 = 1.0f + fminf(r.tau * __builtin_amdgcn_rcpf(r.b4 + es), 1e30f);
+  const float rg = __builtin_amdgcn_rcpf(fmaxf(fmaxf(g1, g2), fmaxf(g3, g4)));
+  const float p1 = share(g1, rg), p2 = share(g2, rg), p3 = share(g3, rg), p4 = share(g4, rg);
+  const float th = float(ISW_CT) * (((p1 + p2) + p3) + p4);
+  const float k1 = p1 >= th ? 4.0f : 0.0f, k2 = p2 >= th ? 2.0f : 0.0f,
+              k3 = p3 >= th ? 3.0f : 0.0f, k4 = p4 >= th ? 1.0f : 0.0f;
+  const float C3 = (5.0f * D - E) * (1.0f / 6.0f);
+  const float C4 = (2.0f * A - 7.0f * B) * (1.0f / 6.0f);
+  return c + s * ((k1 * C1 + k2 * C2 + k3 * C3 + k4 * C4) *
+                  __builtin_amdgcn_rcpf(((k1 + k2) + k3) + k4));
+}
+
 template <typename T>
 __device__ __forceinline__ T weno(T a, T b, T c, T d, T e, int weights,
                                   T eps, bool order3, int& nshort);
@@ -324,12 +447,14 @@ template <>
 __device__ __forceinline__ double weno<double>(double a, double b, double c,
                                                double d, double e, int w,
                                                double eps, bool o3, int& nshort) {
+  if (w == W_CUTOFF) return weno_f64_cutoff(a, b, c, d, e, eps, o3, nshort);
   return weno_f64_fast(a, b, c, d, e, w, eps, o3, nshort);
 }
 template <>
 __device__ __forceinline__ float weno<float>(float a, float b, float c,
                                              float d, float e, int w,
                                              float eps, bool o3, int& nshort) {
+  if (w == W_CUTOFF) return weno_f32_cutoff(a, b, c, d, e, eps, o3, nshort);
   return weno_f32(a, b, c, d, e, w, eps, o3, nshort);
 }
 

@@ -20,6 +20,10 @@ struct LaunchEvents {
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
                         bool readR, hipStream_t s, LaunchEvents ev = {});
 
+// launch_sweep for the cut-off weights (W_CUTOFF).
+hipError_t launch_sweep_cut(int precision, int ndim, int D, const SweepArgs& a, int mode,
+                            bool readR, hipStream_t s, LaunchEvents ev = {});
+
 // One whole RK stage of a 2D grid (x and y faces of each tile in one
 // launch); mode is OUT_RHS or one of the OUT_RK* modes.  Not for the
 // learned weights.

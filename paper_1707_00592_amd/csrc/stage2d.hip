@@ -35,7 +35,7 @@ struct LdsStencil2 {
 
 }  // namespace
 
-template <typename T, int TX, int TY, int NTHR, int MODE>
+template <typename T, int TX, int TY, int NTHR, int MODE, bool CUT>
 __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   constexpr int NDIM = 2, NC = 6;
   constexpr int SX = TX + 6, SY = TY + 6;  // staged rectangle; its corners stay unused
@@ -123,7 +123,8 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
     st.pstride = 1;
     double F[NC], us;
     int n3, n1, nsc;
-    face_flux<T, NDIM, 0>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nsc);
+    face_flux<T, NDIM, 0>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
+                          nsc);
     // a face on a tile boundary is evaluated by both tiles: count it in the
     // tile to its right (the last tile for the domain's last face)
     if (fx < TX || gx0 + fx == nx) {
@@ -169,7 +170,8 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
     st.pstride = SX;
     double F[NC], us;
     int n3, n1, nsc;
-    face_flux<T, NDIM, 1>(st, g.weights, g.mood, g.eps, F, us, n3, n1, nsc);
+    face_flux<T, NDIM, 1>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
+                          nsc);
     if (fy < TY || gy0 + fy == ny) {
       my3[1] += n3;
       my1[1] += n1;
@@ -239,29 +241,37 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
 // 16 x 15 tiles: 255 x faces and 256 y faces, one per lane in each phase.
 constexpr int kTX = 16, kTY = 15, kThreads = 256;
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool CUT>
 static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   const int64_t blocks = ((a.n[0] + kTX - 1) / kTX) * ((a.n[1] + kTY - 1) / kTY);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(kThreads);
   if (ev.start)
-    hipExtLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE>), grid, block, 0, s,
+    hipExtLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT>), grid, block, 0, s,
                           ev.start, ev.stop, 0, a);
   else
-    hipLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_p(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
+template <typename T, bool CUT>
+static hipError_t launch_m(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
   switch (mode) {
-    case OUT_RHS: return launch_t<T, OUT_RHS>(a, s, ev);
-    case OUT_RK1: return launch_t<T, OUT_RK1>(a, s, ev);
-    case OUT_RK2: return launch_t<T, OUT_RK2>(a, s, ev);
-    case OUT_RK3: return launch_t<T, OUT_RK3>(a, s, ev);
+    case OUT_RHS: return launch_t<T, OUT_RHS, CUT>(a, s, ev);
+    case OUT_RK1: return launch_t<T, OUT_RK1, CUT>(a, s, ev);
+    case OUT_RK2: return launch_t<T, OUT_RK2, CUT>(a, s, ev);
+    case OUT_RK3: return launch_t<T, OUT_RK3, CUT>(a, s, ev);
     default: return hipErrorInvalidValue;
   }
+}
+
+// The cut-off weights run in kernels of their own, so that the other forms
+// keep their register allocation.
+template <typename T>
+static hipError_t launch_p(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
+  return a.weights == W_CUTOFF ? launch_m<T, true>(a, mode, s, ev)
+                               : launch_m<T, false>(a, mode, s, ev);
 }
 
 hipError_t launch_stage2d(int precision, const SweepArgs& a, int mode, hipStream_t s,

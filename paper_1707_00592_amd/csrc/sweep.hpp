@@ -293,6 +293,14 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
 // cascade, HLLC.  F (face order) and us are written; o3/o1 report the
 // orders used (per side), nshort the field-sides of the first pass whose
 // reconstruction took its shortcut (weno<T>).
+// The weights a stage kernel evaluates: the cut-off form in the kernels
+// instantiated for it, else eq. (21) or eq. (28) as asked (those kernels
+// never see W_CUTOFF, and the compiler knows it).
+template <bool CUT>
+__device__ __forceinline__ int kernel_weights(int w) {
+  return CUT ? W_CUTOFF : (w == W_BASIC ? W_BASIC : W_MODIFIED);
+}
+
 template <typename T, int NDIM, int D, class S>
 __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
                                           double eps, double* F, double& us,

@@ -18,7 +18,7 @@ LIB_PATH = PKG / "_build" / "libisweno.so"
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NONPHYSICAL = 0, -1, -2, -3, -4
 BC_TRANSMISSIVE, BC_PERIODIC, BC_REFLECTIVE = 0, 1, 2
 FP64, FP32 = 0, 1
-W_MODIFIED, W_BASIC, W_MLP = 0, 1, 2
+W_MODIFIED, W_BASIC, W_MLP, W_CUTOFF = 0, 1, 2, 3
 MLP_NI, MLP_H, MLP_NO = 8, 32, 9
 MLP_NPARAM = 32 * 8 + 32 + 32 * 32 + 32 + 9 * 32 + 9
 
