@@ -117,11 +117,12 @@ def parse():
                          "(for profiling developed states; 0 for the benchmark)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--extras", default="config1,mlp,accuracy,study,paper2d,3d,batch",
+    ap.add_argument("--extras", default="config1,mlp,accuracy,study,mood,paper2d,3d,batch",
                     help="other workloads to report: config1 (the 200-cell gas-liquid shock "
                          "tube), mlp (learned weights, trained here), "
-                         "accuracy (every form against a 2x finer FP64 run), study (basic "
-                         "against modified weights, 1D convergence), paper2d (the paper's 2D "
+                         "accuracy (every form against a 2x finer FP64 run), study (basic, "
+                         "modified and cut-off weights, 1D convergence), mood (cost of the "
+                         "MOOD cascade where fallbacks are common), paper2d (the paper's 2D "
                          "cylinder, droplet and bubble cases at full size), 3d (256^3 "
                          "shock-droplet), batch (4096 uneven tubes); empty for none")
     ap.add_argument("--steps-3d", type=int, default=200,
@@ -772,6 +773,14 @@ def main():
         except Exception as e:
             other["weights_study_1d"] = {"error": repr(e)}
         progress("study", t0)
+    if "mood" in extras:
+        t0 = time.perf_counter()
+        try:
+            from paper_1707_00592_amd import studies
+            other["mood_cost"] = studies.mood_cost_study(ctx)
+        except Exception as e:
+            other["mood_cost"] = {"error": repr(e)}
+        progress("mood", t0)
     if "paper2d" in extras:
         t0 = time.perf_counter()
         try:

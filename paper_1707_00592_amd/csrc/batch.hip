@@ -194,10 +194,14 @@ static hipError_t launch_stage_tl(const BatchArgs& a, int mode, int blocks, hipS
 template <typename T>
 static hipError_t launch_stage_t(int tl, const BatchArgs& a, int mode, int blocks,
                                  hipStream_t s) {
+  // the tile list was cut for exactly this tile length (a kernel for a
+  // shorter one would overrun its LDS on the list's longer tiles)
+  if (blocks < 1) return hipErrorInvalidValue;
   switch (tl) {
     case 63: return launch_stage_tl<T, 63>(a, mode, blocks, s);
     case 127: return launch_stage_tl<T, 127>(a, mode, blocks, s);
-    default: return launch_stage_tl<T, 255>(a, mode, blocks, s);
+    case 255: return launch_stage_tl<T, 255>(a, mode, blocks, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

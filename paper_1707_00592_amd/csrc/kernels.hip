@@ -88,6 +88,7 @@ hipError_t launch_zero_u64(unsigned long long* w, hipStream_t s) {
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
                       double cfl, double dt_max, unsigned long long* maxbits, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev) {
+  if (n[0] < 1 || n[1] < 1 || n[2] < 1 || ncu < 1) return hipErrorInvalidValue;
   const int64_t N = n[0] * n[1] * n[2];
   int64_t blocks = (N + 1023) / 1024;
   // one workgroup per CU: every workgroup ends in one atomic on the same

@@ -243,6 +243,9 @@ constexpr int kTX = 16, kTY = 15, kThreads = 256;
 
 template <typename T, int MODE, bool CUT>
 static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
+  // one workgroup per tile: the kernel maps block b to tile (b & 7, b >> 3)
+  // of the XCD-ordered list of exactly this many tiles
+  if (a.n[0] < 1 || a.n[1] < 1 || a.n[2] != 1) return hipErrorInvalidValue;
   const int64_t blocks = ((a.n[0] + kTX - 1) / kTX) * ((a.n[1] + kTY - 1) / kTY);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;

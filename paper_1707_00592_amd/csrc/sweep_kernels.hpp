@@ -410,6 +410,11 @@ template <typename T, int NDIM, int D, int MODE, bool READ_R, bool LEARNED, bool
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   using TS = TileShape<NDIM, D>;
   constexpr int NTHR = 256;
+  // the tile decomposition below covers [0, n) on every axis and the kernel
+  // bounds each access by n; axes beyond NDIM must be 1
+  if (a.n[0] < 1 || a.n[1] < 1 || a.n[2] < 1 || (NDIM < 2 && a.n[1] != 1) ||
+      (NDIM < 3 && a.n[2] != 1))
+    return hipErrorInvalidValue;
   const int64_t nL = a.n[D];
   int64_t nA, nT;
   if (D == 0) { nA = a.n[1] * a.n[2]; nT = 1; }

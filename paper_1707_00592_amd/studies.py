@@ -58,3 +58,59 @@ def weights_study(ctx: isweno.Context):
                                      "max": [x[1] for x in e],
                                      "orders": np.log2(l1[:-1] / l1[1:]).round(2).tolist()}
     return res
+
+
+def mood_cost_study(ctx: isweno.Context, fracs=(0.0, 0.001, 0.01, 0.1, 1.0), reps: int = 20):
+    """Cost of the MOOD cascade (Sec. 3.4) where its fallbacks are common.
+
+    The 1024 x 512 shock-bubble start state with a fraction of its cells
+    replaced by independent random two-phase states (water or air, |u|, |v|
+    up to 2000 m/s, p from 1e4 to 3e9 Pa): one FP64 RHS (the fused 2D
+    stage kernel) timed with the cascade on and off, with the fallback
+    counts.  The redo of a failing face side is a divergent branch inside
+    its wave, so its cost follows the waves that hold a failing side, not
+    the failing sides themselves."""
+    import torch
+    base = workloads.shock_bubble_2d(1024, 512)
+    g = isweno.make_grid(base.n, base.dx, base.bc_lo, base.bc_hi)
+    sides = 2 * ((base.n[0] + 1) * base.n[1] + base.n[0] * (base.n[1] + 1))
+    rs = np.random.default_rng(1707)
+    out = {"workload": "2D shock-bubble 1024x512 start state, a fraction of the cells "
+                       "replaced by random two-phase states; one FP64 RHS",
+           "reps": reps, "rows": []}
+    for f in fracs:
+        U = base.U.copy()
+        m = rs.random(base.ncells) < f
+        k = int(m.sum())
+        if k:
+            rho = np.where(rs.random(k) < 0.5, 1000.0, 1.0) * rs.uniform(0.5, 2.0, k)
+            water = rho > 100.0
+            vel = [rs.uniform(-2000.0, 2000.0, k), rs.uniform(-2000.0, 2000.0, k)]
+            p = 10.0 ** rs.uniform(4.0, 9.5, k)
+            U[:, m] = workloads.prim_to_cons(rho, vel, p, np.where(water, 4.4, 1.4),
+                                             np.where(water, 6e8, 0.0))
+        Ud = torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+        row = {"fraction": f, "cells": k}
+        for mood in (True, False):
+            o = isweno.make_opts(mood=mood)
+            ctx.rhs(Ud, g, o)                       # warm
+            torch.cuda.synchronize()
+            st = isweno.new_stats()
+            ctx.timing_enable(True)
+            for _ in range(reps):
+                ctx.rhs(Ud, g, o, stats=st)
+            torch.cuda.synchronize()
+            ms, n = ctx.timing_read(isweno.K_STAGE2D)
+            ctx.timing_enable(False)
+            s = isweno.read_stats(st)
+            key = "mood_on" if mood else "mood_off"
+            row[key] = {"stage_us": 1e3 * ms / n}
+            if mood:
+                o3 = sum(s.o3[:2]) / reps
+                o1 = sum(s.o1[:2]) / reps
+                row[key].update({"order3_sides": o3, "order1_sides": o1,
+                                 "fallback_fraction": (o3 + o1) / sides})
+        row["cascade_cost_us"] = row["mood_on"]["stage_us"] - row["mood_off"]["stage_us"]
+        out["rows"].append(row)
+        del Ud
+    return out
