@@ -102,6 +102,7 @@ def load() -> C.CDLL:
                                   C.POINTER(C.c_int)]
     lib.or_exact_star.argtypes = [_dp, _dp, _dp, _dp]
     lib.or_exact_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
+    lib.or_exact_sample_n.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp, C.c_long, _dp]
     lib.or_mlp_forward.argtypes = [_dp, _dp, C.c_long, _dp]
     lib.or_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, C.c_long, _dp]
     lib.or_mlp_loss_grad.restype = C.c_double
@@ -291,12 +292,9 @@ def exact_sample(WL, WR, xi):
     """Exact solution at x/t = xi (array) -> array (len(xi), 5)."""
     WL = _f64(WL); WR = _f64(WR)
     ps, us = exact_star(WL, WR)
-    xi = np.atleast_1d(np.asarray(xi, dtype=np.float64))
-    out = np.zeros((xi.size, 5)); w = np.zeros(5)
-    lib = load()
-    for i, x in enumerate(xi):
-        lib.or_exact_sample(_ptr(WL), _ptr(WR), ps, us, float(x), _ptr(w))
-        out[i] = w
+    xi = _f64(np.atleast_1d(xi))
+    out = np.zeros((xi.size, 5))
+    load().or_exact_sample_n(_ptr(WL), _ptr(WR), ps, us, _ptr(xi), xi.size, _ptr(out))
     return out
 
 

@@ -160,3 +160,10 @@ void or_exact_sample(const double WL[5], const double WR[5], double pstar,
     }
   }
 }
+
+/* The same at n similarity coordinates xi[i]; W is n x 5, row-major. */
+void or_exact_sample_n(const double WL[5], const double WR[5], double pstar,
+                       double ustar, const double *xi, long n, double *W) {
+  long i;
+  for (i = 0; i < n; i++) or_exact_sample(WL, WR, pstar, ustar, xi[i], W + 5 * i);
+}

@@ -133,6 +133,9 @@ int or_exact_star(const double WL[5], const double WR[5], double *pstar,
                   double *ustar);
 void or_exact_sample(const double WL[5], const double WR[5], double pstar,
                      double ustar, double xi, double W[5]);
+/* or_exact_sample at n coordinates xi[0..n-1]; W is n x 5, row-major. */
+void or_exact_sample_n(const double WL[5], const double WR[5], double pstar,
+                       double ustar, const double *xi, long n, double *W);
 
 /* ---- reference MLP for the learned-weights form (FP64) ----
  * Layout of params (float64): W1[H][NI], b1[H], W2[H][H], b2[H],
