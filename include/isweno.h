@@ -120,7 +120,13 @@ typedef struct {
 typedef struct {
   int32_t precision; /* ISWENO_FP64 or ISWENO_FP32 */
   int32_t weights;   /* ISWENO_W_* */
-  int32_t mood;      /* 1: MOOD-type positivity cascade of Sec. 3.4 */
+  int32_t mood;      /* 1: MOOD-type positivity cascade of Sec. 3.4, each
+                        failing face side redone inside its wave;
+                        2: the same cascade with the failing faces of a
+                        tile gathered and redone by full waves after the
+                        tile's faces (the fused 2D stage; elsewhere as 1):
+                        the same results, faster only where fallbacks are
+                        dense; 0: off */
   int32_t reserved;  /* must be 0 */
   double eps;        /* epsilon in eqs. (21)/(28); the paper leaves it open,
                         1e-40 is the default reading */

@@ -90,7 +90,7 @@ int check_opts(const isweno_opts* o) {
   if (!o || o->reserved != 0 || o->reserved2 != 0) return ISWENO_ERR_ARG;
   if (o->precision != ISWENO_FP64 && o->precision != ISWENO_FP32) return ISWENO_ERR_ARG;
   if (o->weights < 0 || o->weights > 3) return ISWENO_ERR_ARG;
-  if (o->mood != 0 && o->mood != 1) return ISWENO_ERR_ARG;
+  if (o->mood < 0 || o->mood > 2) return ISWENO_ERR_ARG;
   if (!(o->eps >= 0.0)) return ISWENO_ERR_ARG;
   if (o->weights == ISWENO_W_MLP) {
     // the learned weights run with the float32 reconstruction only

@@ -281,7 +281,7 @@ static int build_table(isweno_batch_plan* p, int tl) {
 static int check_batch_opts(const isweno_opts* o) {
   if (!o || o->reserved != 0 || o->reserved2 != 0) return ISWENO_ERR_ARG;
   if (o->precision != ISWENO_FP64 && o->precision != ISWENO_FP32) return ISWENO_ERR_ARG;
-  if (o->weights < 0 || o->weights > 3 || (o->mood != 0 && o->mood != 1)) return ISWENO_ERR_ARG;
+  if (o->weights < 0 || o->weights > 3 || o->mood < 0 || o->mood > 2) return ISWENO_ERR_ARG;
   if (!(o->eps >= 0.0)) return ISWENO_ERR_ARG;
   if (o->weights == ISWENO_W_MLP) return ISWENO_ERR_UNSUPPORTED;
   return ISWENO_OK;

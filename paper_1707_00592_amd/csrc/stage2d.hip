@@ -35,7 +35,7 @@ struct LdsStencil2 {
 
 }  // namespace
 
-template <typename T, int TX, int TY, int NTHR, int MODE, bool CUT>
+template <typename T, int TX, int TY, int NTHR, int MODE, bool CUT, bool GATHER>
 __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   constexpr int NDIM = 2, NC = 6;
   constexpr int SX = TX + 6, SY = TY + 6;  // staged rectangle; its corners stay unused
@@ -51,6 +51,10 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   __shared__ T sf[(NC + 1) * NFMAX];
   __shared__ int s_status;
   __shared__ int s_skip;
+  // GATHER: faces whose MOOD check failed, per phase (face index | fail
+  // bits << 16), redone by full waves after the phase's faces
+  __shared__ int s_queue[GATHER ? NFMAX : 1];
+  __shared__ int s_nq[GATHER ? 2 : 1];
 
   const int64_t nx = g.n[0], ny = g.n[1], N = nx * ny;
   // Tile order.  The hardware deals workgroups to its 8 XCDs in turn
@@ -74,6 +78,10 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   const int64_t gy0 = (cls + 8 * (prow - first)) * TY;
   const int tid = threadIdx.x;
   if (tid == 0) {
+    if constexpr (GATHER) {
+      s_nq[0] = 0;
+      s_nq[1] = 0;
+    }
     s_status = ST_OK;
     // sticky failure: one read per workgroup so that all lanes agree
     s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
@@ -113,30 +121,93 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
 
   int my3[2] = {0, 0}, my1[2] = {0, 0}, mys[2] = {0, 0};
 
-  // 2. x faces: face (fx, y) lies between cells fx-1 and fx of row y
-  for (int f = tid; f < NFX; f += NTHR) {
-    const int y = f / (TX + 1), fx = f % (TX + 1);
-    if (!(gy0 + y < ny && gx0 + fx <= nx)) continue;
-    LdsStencil2 st;
-    st.base = &sq[(y + 3) * SX + fx];
-    st.cstride = QROW;
-    st.pstride = 1;
-    double F[NC], us;
-    int n3, n1, nsc;
-    face_flux<T, NDIM, 0>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
-                          nsc);
-    // a face on a tile boundary is evaluated by both tiles: count it in the
-    // tile to its right (the last tile for the domain's last face)
-    if (fx < TX || gx0 + fx == nx) {
-      my3[0] += n3;
-      my1[0] += n1;
-      mys[0] += nsc;
-    }
+  const int wts = kernel_weights<CUT>(g.weights);
+  // a face whose check failed joins the phase's queue: one LDS atomic per
+  // wave, slots in lane order (GATHER only)
+  auto enqueue = [&](int d, int f, int fail) {
+    const unsigned long long bal = __ballot(fail != 0);
+    if (bal == 0) return;
+    const int lane = tid & 63, lead = __builtin_ctzll(bal);
+    int base = 0;
+    if (lane == lead) base = atomicAdd(&s_nq[d], __popcll(bal));
+    base = __shfl(base, lead);
+    if (fail) s_queue[base + __popcll(bal & ((1ull << lane) - 1))] = f | (fail << 16);
+  };
+  auto store = [&](int f, const double* F, double us) {
 #pragma unroll
     for (int k = 0; k < NC; k++) sf[k * NFMAX + f] = T(F[k]);
     sf[NC * NFMAX + f] = T(us);
+  };
+  auto xstencil = [&](int f) {
+    LdsStencil2 st;
+    st.base = &sq[(f / (TX + 1) + 3) * SX + f % (TX + 1)];
+    st.cstride = QROW;
+    st.pstride = 1;
+    return st;
+  };
+  auto ystencil = [&](int f) {
+    LdsStencil2 st;
+    st.base = &sq[(f / TX) * SX + f % TX + 3];
+    st.cstride = QROW;
+    st.pstride = SX;
+    return st;
+  };
+  // a face on a tile boundary is evaluated by both tiles: it is counted in
+  // the tile after it (the last tile for the domain's last face)
+  auto xcounted = [&](int f) {
+    const int fx = f % (TX + 1);
+    return fx < TX || gx0 + fx == nx;
+  };
+  auto ycounted = [&](int f) {
+    const int fy = f / TX;
+    return fy < TY || gy0 + fy == ny;
+  };
+
+  // 2. x faces: face (fx, y) lies between cells fx-1 and fx of row y
+  if constexpr (GATHER) {
+    for (int f0 = 0; f0 < NFX; f0 += NTHR) {
+      const int f = f0 + tid;
+      int fail = 0;
+      if (f < NFX && gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx) {
+        double F[NC], us;
+        int nsc;
+        fail = face_flux_first<T, NDIM, 0>(xstencil(f), wts, g.eps, F, us, nsc);
+        if (xcounted(f)) mys[0] += nsc;
+        if (!fail) store(f, F, us);
+      }
+      enqueue(0, f, fail);
+    }
+    __syncthreads();
+    const int nq = s_nq[0];
+    if (nq) {
+      for (int q = tid; q < nq; q += NTHR) {
+        const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
+        double F[NC], us;
+        int n3, n1;
+        face_flux_redo<T, NDIM, 0>(xstencil(f), fail, wts, g.eps, F, us, n3, n1);
+        if (xcounted(f)) {
+          my3[0] += n3;
+          my1[0] += n1;
+        }
+        store(f, F, us);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int f = tid; f < NFX; f += NTHR) {
+      if (!(gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx)) continue;
+      double F[NC], us;
+      int n3, n1, nsc;
+      face_flux<T, NDIM, 0>(xstencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+      if (xcounted(f)) {
+        my3[0] += n3;
+        my1[0] += n1;
+        mys[0] += nsc;
+      }
+      store(f, F, us);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // x terms of eqs. (5)-(6) per cell, kept in registers (axis order; for
   // the x axis face order and axis order coincide)
@@ -161,25 +232,45 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
   __syncthreads();
 
   // 3. y faces: face (x, fy) lies between cells fy-1 and fy of column x
-  for (int f = tid; f < NFY; f += NTHR) {
-    const int fy = f / TX, x = f % TX;
-    if (!(gx0 + x < nx && gy0 + fy <= ny)) continue;
-    LdsStencil2 st;
-    st.base = &sq[fy * SX + x + 3];
-    st.cstride = QROW;
-    st.pstride = SX;
-    double F[NC], us;
-    int n3, n1, nsc;
-    face_flux<T, NDIM, 1>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
-                          nsc);
-    if (fy < TY || gy0 + fy == ny) {
-      my3[1] += n3;
-      my1[1] += n1;
-      mys[1] += nsc;
+  if constexpr (GATHER) {
+    for (int f0 = 0; f0 < NFY; f0 += NTHR) {
+      const int f = f0 + tid;
+      int fail = 0;
+      if (f < NFY && gx0 + f % TX < nx && gy0 + f / TX <= ny) {
+        double F[NC], us;
+        int nsc;
+        fail = face_flux_first<T, NDIM, 1>(ystencil(f), wts, g.eps, F, us, nsc);
+        if (ycounted(f)) mys[1] += nsc;
+        if (!fail) store(f, F, us);
+      }
+      enqueue(1, f, fail);
     }
-#pragma unroll
-    for (int k = 0; k < NC; k++) sf[k * NFMAX + f] = T(F[k]);
-    sf[NC * NFMAX + f] = T(us);
+    __syncthreads();
+    const int nq = s_nq[1];
+    for (int q = tid; q < nq; q += NTHR) {
+      const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
+      double F[NC], us;
+      int n3, n1;
+      face_flux_redo<T, NDIM, 1>(ystencil(f), fail, wts, g.eps, F, us, n3, n1);
+      if (ycounted(f)) {
+        my3[1] += n3;
+        my1[1] += n1;
+      }
+      store(f, F, us);
+    }
+  } else {
+    for (int f = tid; f < NFY; f += NTHR) {
+      if (!(gx0 + f % TX < nx && gy0 + f / TX <= ny)) continue;
+      double F[NC], us;
+      int n3, n1, nsc;
+      face_flux<T, NDIM, 1>(ystencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+      if (ycounted(f)) {
+        my3[1] += n3;
+        my1[1] += n1;
+        mys[1] += nsc;
+      }
+      store(f, F, us);
+    }
   }
   if (g.stats && g.mood) {
     const unsigned long long b = __ballot((my3[0] | my1[0] | my3[1] | my1[1]) != 0);
@@ -241,7 +332,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
 // 16 x 15 tiles: 255 x faces and 256 y faces, one per lane in each phase.
 constexpr int kTX = 16, kTY = 15, kThreads = 256;
 
-template <typename T, int MODE, bool CUT>
+template <typename T, int MODE, bool CUT, bool GATHER>
 static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   // one workgroup per tile: the kernel maps block b to tile (b & 7, b >> 3)
   // of the XCD-ordered list of exactly this many tiles
@@ -251,22 +342,29 @@ static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(kThreads);
   if (ev.start)
-    hipExtLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT>), grid, block, 0, s,
+    hipExtLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT, GATHER>), grid, block, 0, s,
                           ev.start, ev.stop, 0, a);
   else
-    hipLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT, GATHER>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
-template <typename T, bool CUT>
-static hipError_t launch_m(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
+template <typename T, bool CUT, bool GATHER>
+static hipError_t launch_g(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
   switch (mode) {
-    case OUT_RHS: return launch_t<T, OUT_RHS, CUT>(a, s, ev);
-    case OUT_RK1: return launch_t<T, OUT_RK1, CUT>(a, s, ev);
-    case OUT_RK2: return launch_t<T, OUT_RK2, CUT>(a, s, ev);
-    case OUT_RK3: return launch_t<T, OUT_RK3, CUT>(a, s, ev);
+    case OUT_RHS: return launch_t<T, OUT_RHS, CUT, GATHER>(a, s, ev);
+    case OUT_RK1: return launch_t<T, OUT_RK1, CUT, GATHER>(a, s, ev);
+    case OUT_RK2: return launch_t<T, OUT_RK2, CUT, GATHER>(a, s, ev);
+    case OUT_RK3: return launch_t<T, OUT_RK3, CUT, GATHER>(a, s, ev);
     default: return hipErrorInvalidValue;
   }
+}
+
+// mood 2: the gathered cascade, in kernels of its own
+template <typename T, bool CUT>
+static hipError_t launch_m(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev) {
+  return a.mood == 2 ? launch_g<T, CUT, true>(a, mode, s, ev)
+                     : launch_g<T, CUT, false>(a, mode, s, ev);
 }
 
 // The cut-off weights run in kernels of their own, so that the other forms

@@ -380,4 +380,93 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
   us = double(tus);
 }
 
+// The same face in two passes, for a kernel that gathers the faces the
+// MOOD cascade needs and redoes them by full waves.  First pass: the
+// 5th-order states and their check; a face with a failing side returns its
+// fail bits (non-zero) and no flux.  Second pass (face_flux_redo, on the
+// gathered faces): the 5th-order states are formed again (the same bits),
+// the failing sides go through the cascade, then HLLC -- the flux that
+// face_flux gives, bit for bit.
+template <typename T, int NDIM, class S>
+__device__ __forceinline__ void face_params(const S& st, T& a, T& b, double& bd, double& gd) {
+  constexpr int CR = 0, CP = 1 + NDIM, CG = 2 + NDIM, CPI = 3 + NDIM;
+  const double rb = 0.5 * (st(CR, 2) + st(CR, 3));
+  const double pb = 0.5 * (st(CP, 2) + st(CP, 3));
+  const double Gb = 0.5 * (st(CG, 2) + st(CG, 3));
+  const double Pb = 0.5 * (st(CPI, 2) + st(CPI, 3));
+  const T c2 = sound2<T>(T(rb), T(pb), T(Gb), T(Pb));
+  const T c = sqrt(c2);
+  a = T(rb) * c / T(2);
+  b = qdiv<T>(T(1), c2);
+  bd = double(b);
+  gd = 1.0 / double(T(rb) * c);
+  if (sizeof(T) == 8) {
+    bd = 1.0 / double(c2);
+  }
+}
+
+template <typename T, int NDIM, int D, class S>
+__device__ __forceinline__ int face_flux_first(const S& st, int weights, double eps, double* F,
+                                               double& us, int& nshort) {
+  constexpr int NT = NDIM - 1, NC = 5 + NT;
+  T a, b;
+  double bd, gd;
+  face_params<T, NDIM>(st, a, b, bd, gd);
+  double ql[NC], qr[NC];
+  nshort = 0;
+  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort);
+  const int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
+                   (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
+  if (fail) return fail;
+  T tl[NC], tr[NC], tF[NC], tus;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    tl[k] = T(ql[k]);
+    tr[k] = T(qr[k]);
+  }
+  hllc<T, NT>(tl, tr, tF, tus);
+#pragma unroll
+  for (int k = 0; k < NC; k++) F[k] = double(tF[k]);
+  us = double(tus);
+  return 0;
+}
+
+template <typename T, int NDIM, int D, class S>
+__device__ __forceinline__ void face_flux_redo(const S& st, int fail, int weights, double eps,
+                                               double* F, double& us, int& n3, int& n1) {
+  constexpr int NT = NDIM - 1, NC = 5 + NT;
+  T a, b;
+  double bd, gd;
+  face_params<T, NDIM>(st, a, b, bd, gd);
+  double ql[NC], qr[NC];
+  int nsc = 0, nf3 = 0;
+  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nsc);
+  recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
+  n3 = 0;
+  n1 = 0;
+#pragma unroll
+  for (int side = 0; side < 2; side++) {
+    if (!(fail & (1 << side))) continue;
+    double* q = side ? qr : ql;
+    const int ok = admissible(q[0], q[2 + NT], q[3 + NT], q[4 + NT]) ? 1 : 0;
+    if (!ok) {
+      const int j = side ? 3 : 2;
+#pragma unroll
+      for (int k = 0; k < NC; k++) q[k] = st(axis_comp<NDIM, D>(k), j);
+    }
+    n3 += ok;
+    n1 += 1 - ok;
+  }
+  T tl[NC], tr[NC], tF[NC], tus;
+#pragma unroll
+  for (int k = 0; k < NC; k++) {
+    tl[k] = T(ql[k]);
+    tr[k] = T(qr[k]);
+  }
+  hllc<T, NT>(tl, tr, tF, tus);
+#pragma unroll
+  for (int k = 0; k < NC; k++) F[k] = double(tF[k]);
+  us = double(tus);
+}
+
 }  // namespace isw

@@ -19,6 +19,7 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_DEVICE, ERR_NONPHYSICAL = 0, -1, -2, -3, -4
 BC_TRANSMISSIVE, BC_PERIODIC, BC_REFLECTIVE = 0, 1, 2
 FP64, FP32 = 0, 1
 W_MODIFIED, W_BASIC, W_MLP, W_CUTOFF = 0, 1, 2, 3
+MOOD_OFF, MOOD_ON, MOOD_GATHER = 0, 1, 2
 MLP_NI, MLP_H, MLP_NO = 8, 32, 9
 MLP_NPARAM = 32 * 8 + 32 + 32 * 32 + 32 + 9 * 32 + 9
 
@@ -134,7 +135,9 @@ def make_grid(n, dx, bc_lo=0, bc_hi=0) -> Grid:
 def make_opts(precision=FP64, weights=W_MODIFIED, mood=True, eps=1e-40, cfl=0.5,
               dt_max=0.0, mlp_params=None, mlp_conf_threshold=0.5) -> Opts:
     o = Opts()
-    o.precision, o.weights, o.mood = int(precision), int(weights), int(bool(mood))
+    # mood: False/True (0/1), or MOOD_GATHER (2) for the gathered redo
+    o.precision, o.weights = int(precision), int(weights)
+    o.mood = int(mood) if mood == MOOD_GATHER else int(bool(mood))
     o.reserved = 0
     o.eps, o.cfl, o.dt_max = float(eps), float(cfl), float(dt_max)
     o.mlp_params = None if mlp_params is None else int(mlp_params.data_ptr())

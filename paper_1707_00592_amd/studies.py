@@ -67,9 +67,9 @@ def mood_cost_study(ctx: isweno.Context, fracs=(0.0, 0.001, 0.01, 0.1, 1.0), rep
     replaced by independent random two-phase states (water or air, |u|, |v|
     up to 2000 m/s, p from 1e4 to 3e9 Pa): one FP64 RHS (the fused 2D
     stage kernel) timed with the cascade on and off, with the fallback
-    counts.  The redo of a failing face side is a divergent branch inside
-    its wave, so its cost follows the waves that hold a failing side, not
-    the failing sides themselves."""
+    counts, and with the gathered cascade (mood = 2).  The redo of a failing
+    face side is a divergent branch inside its wave, so its cost follows the
+    waves that hold a failing side, not the failing sides themselves."""
     import torch
     base = workloads.shock_bubble_2d(1024, 512)
     g = isweno.make_grid(base.n, base.dx, base.bc_lo, base.bc_hi)
@@ -91,7 +91,7 @@ def mood_cost_study(ctx: isweno.Context, fracs=(0.0, 0.001, 0.01, 0.1, 1.0), rep
                                              np.where(water, 6e8, 0.0))
         Ud = torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
         row = {"fraction": f, "cells": k}
-        for mood in (True, False):
+        for mood in (isweno.MOOD_ON, isweno.MOOD_OFF, isweno.MOOD_GATHER):
             o = isweno.make_opts(mood=mood)
             ctx.rhs(Ud, g, o)                       # warm
             torch.cuda.synchronize()
@@ -103,14 +103,17 @@ def mood_cost_study(ctx: isweno.Context, fracs=(0.0, 0.001, 0.01, 0.1, 1.0), rep
             ms, n = ctx.timing_read(isweno.K_STAGE2D)
             ctx.timing_enable(False)
             s = isweno.read_stats(st)
-            key = "mood_on" if mood else "mood_off"
+            key = {isweno.MOOD_ON: "mood_on", isweno.MOOD_OFF: "mood_off",
+                   isweno.MOOD_GATHER: "mood_gathered"}[mood]
             row[key] = {"stage_us": 1e3 * ms / n}
-            if mood:
+            if mood == isweno.MOOD_ON:
                 o3 = sum(s.o3[:2]) / reps
                 o1 = sum(s.o1[:2]) / reps
                 row[key].update({"order3_sides": o3, "order1_sides": o1,
                                  "fallback_fraction": (o3 + o1) / sides})
         row["cascade_cost_us"] = row["mood_on"]["stage_us"] - row["mood_off"]["stage_us"]
+        row["gathered_cascade_cost_us"] = (row["mood_gathered"]["stage_us"]
+                                           - row["mood_off"]["stage_us"])
         out["rows"].append(row)
         del Ud
     return out

@@ -117,6 +117,45 @@ def test_rhs_mood_fallback_counts(lib, ctx):
     assert (s.o3[0], s.o1[0]) == (ost.o3[0], ost.o1[0])
 
 
+def _wild_2d(n, frac, seed):
+    """A 2D two-phase state whose cells are, with probability frac, random
+    water or air states (|u|, |v| up to 2000 m/s, p from 1e4 to 3e9 Pa) --
+    dense MOOD fallbacks -- and otherwise water at rest."""
+    rs = np.random.default_rng(seed)
+    N = n[0] * n[1]
+    m = rs.random(N) < frac
+    rho = np.where(m, np.where(rs.random(N) < 0.5, 1000.0, 1.0) * rs.uniform(0.5, 2, N), 1000.0)
+    water = rho > 100
+    u = np.where(m, rs.uniform(-2000, 2000, N), 0.0)
+    v = np.where(m, rs.uniform(-2000, 2000, N), 0.0)
+    p = np.where(m, 10 ** rs.uniform(4, 9.5, N), 1e5)
+    return wl.prim_to_cons(rho, [u, v], p, np.where(water, 4.4, 1.4), np.where(water, 6e8, 0.0))
+
+
+@pytest.mark.parametrize("n,frac,bc", [((150, 70), 1.0, 0), ((33, 46), 0.3, 2), ((64, 15), 1.0, 1),
+                                       ((1024, 512), 0.1, 0)])
+@pytest.mark.parametrize("weights", [oracle.W_MODIFIED, oracle.W_CUTOFF])
+def test_gathered_cascade_matches_oracle(lib, ctx, n, frac, bc, weights):
+    """mood = 2 (the failing faces of a tile gathered and redone by full
+    waves): the oracle's cascade bit for bit, with equal counts, on states
+    where fallbacks are dense (up to a tenth of the face sides)."""
+    U0 = _wild_2d(n, frac, seed=n[0] + 7 * bc)
+    dx = (1.0 / n[0], 1.0 / n[1])
+    og = oracle.make_grid(n, dx, (bc, bc), (bc, bc))
+    ig = lib.make_grid(n, dx, (bc, bc), (bc, bc))
+    oracle.threads(16)
+    ref, ost = oracle.rhs(U0, og, oracle.make_opts(weights=weights))
+    st = lib.new_stats()
+    got = ctx.rhs(_dev(U0), ig, lib.make_opts(weights=weights, mood=lib.MOOD_GATHER),
+                  stats=st).cpu().numpy()
+    s = lib.read_stats(st)
+    print(f"[gather] {n} frac={frac} bc={bc} w={weights}: o3={list(ost.o3[:2])} "
+          f"o1={list(ost.o1[:2])}", flush=True)
+    assert sum(ost.o1[:2]) > 0
+    _check(got, ref, what=f"gathered cascade {n} frac={frac}")
+    assert list(s.o3[:2]) == list(ost.o3[:2]) and list(s.o1[:2]) == list(ost.o1[:2])
+
+
 def test_cfl_dt_matches_oracle(lib, ctx):
     torch = _torch()
     for shape in [(300,), (150, 70), (20, 18, 17)]:
