@@ -92,7 +92,8 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       st.cstride = NP;
       double F[NC], us;
       int n3, n1, nf;
-      face_flux<T, 1, 0>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1, nf);
+      face_flux<T, 1, 0, CUT>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
+                              nf);
       if (j < len || l0 + j == n) {  // count each face of a problem once
         my3 += n3;
         my1 += n1;

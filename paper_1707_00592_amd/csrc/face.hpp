@@ -447,14 +447,12 @@ template <>
 __device__ __forceinline__ double weno<double>(double a, double b, double c,
                                                double d, double e, int w,
                                                double eps, bool o3, int& nshort) {
-  if (w == W_CUTOFF) return weno_f64_cutoff(a, b, c, d, e, eps, o3, nshort);
   return weno_f64_fast(a, b, c, d, e, w, eps, o3, nshort);
 }
 template <>
 __device__ __forceinline__ float weno<float>(float a, float b, float c,
                                              float d, float e, int w,
                                              float eps, bool o3, int& nshort) {
-  if (w == W_CUTOFF) return weno_f32_cutoff(a, b, c, d, e, eps, o3, nshort);
   return weno_f32(a, b, c, d, e, w, eps, o3, nshort);
 }
 
@@ -611,6 +609,20 @@ __device__ __forceinline__ void hllc(const T* ql, const T* qr, T* F, T& us) {
 #pragma unroll
     for (int k = 0; k < NC; k++) F[k] = T(0.5) * Fl[k] + T(0.5) * Fr[k];
     us = T(0.5) * usl + T(0.5) * usr;
+  }
+}
+
+// The reconstruction a stage kernel evaluates: the cut-off form (a
+// compile-time choice: its kernels are instantiated apart), or weno<T> with
+// the eq. (21)/(28) weights.
+template <typename T, bool CUT>
+__device__ __forceinline__ T weno_sel(T a, T b, T c, T d, T e, int weights, T eps, bool order3,
+                                      int& nshort) {
+  if constexpr (CUT) {
+    if constexpr (sizeof(T) == 8) return weno_f64_cutoff(a, b, c, d, e, eps, order3, nshort);
+    else return weno_f32_cutoff(a, b, c, d, e, eps, order3, nshort);
+  } else {
+    return weno<T>(a, b, c, d, e, weights, eps, order3, nshort);
   }
 }
 

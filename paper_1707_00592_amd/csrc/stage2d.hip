@@ -36,7 +36,7 @@ struct LdsStencil2 {
 }  // namespace
 
 template <typename T, int TX, int TY, int NTHR, int MODE, bool CUT, bool GATHER>
-__global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
+__global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(SweepArgs g) {
   constexpr int NDIM = 2, NC = 6;
   constexpr int SX = TX + 6, SY = TY + 6;  // staged rectangle; its corners stay unused
   constexpr int QROW = SX * SY;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
       if (f < NFX && gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx) {
         double F[NC], us;
         int nsc;
-        fail = face_flux_first<T, NDIM, 0>(xstencil(f), wts, g.eps, F, us, nsc);
+        fail = face_flux_first<T, NDIM, 0, CUT>(xstencil(f), wts, g.eps, F, us, nsc);
         if (xcounted(f)) mys[0] += nsc;
         if (!fail) store(f, F, us);
       }
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
         const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
         double F[NC], us;
         int n3, n1;
-        face_flux_redo<T, NDIM, 0>(xstencil(f), fail, wts, g.eps, F, us, n3, n1);
+        face_flux_redo<T, NDIM, 0, CUT>(xstencil(f), fail, wts, g.eps, F, us, n3, n1);
         if (xcounted(f)) {
           my3[0] += n3;
           my1[0] += n1;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
       if (!(gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx)) continue;
       double F[NC], us;
       int n3, n1, nsc;
-      face_flux<T, NDIM, 0>(xstencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+      face_flux<T, NDIM, 0, CUT>(xstencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
       if (xcounted(f)) {
         my3[0] += n3;
         my1[0] += n1;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
       if (f < NFY && gx0 + f % TX < nx && gy0 + f / TX <= ny) {
         double F[NC], us;
         int nsc;
-        fail = face_flux_first<T, NDIM, 1>(ystencil(f), wts, g.eps, F, us, nsc);
+        fail = face_flux_first<T, NDIM, 1, CUT>(ystencil(f), wts, g.eps, F, us, nsc);
         if (ycounted(f)) mys[1] += nsc;
         if (!fail) store(f, F, us);
       }
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
       const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
       double F[NC], us;
       int n3, n1;
-      face_flux_redo<T, NDIM, 1>(ystencil(f), fail, wts, g.eps, F, us, n3, n1);
+      face_flux_redo<T, NDIM, 1, CUT>(ystencil(f), fail, wts, g.eps, F, us, n3, n1);
       if (ycounted(f)) {
         my3[1] += n3;
         my1[1] += n1;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(NTHR) void stage2d_kernel(SweepArgs g) {
       if (!(gx0 + f % TX < nx && gy0 + f / TX <= ny)) continue;
       double F[NC], us;
       int n3, n1, nsc;
-      face_flux<T, NDIM, 1>(ystencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+      face_flux<T, NDIM, 1, CUT>(ystencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
       if (ycounted(f)) {
         my3[1] += n3;
         my1[1] += n1;

@@ -215,7 +215,7 @@ __device__ __forceinline__ void mlp_field(const T* w, MlpRun& mr, T eps, T& rl, 
   }
 }
 
-template <typename T, int NDIM, int D, class S>
+template <typename T, int NDIM, int D, bool CUT = false, class S>
 __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int weights, T eps,
                                       T a, T b, double bd, double gd, double* ql, double* qr,
                                       int& nshort, MlpRun* mr = nullptr) {
@@ -266,8 +266,8 @@ __device__ __forceinline__ void recon(const S& st, int sides, bool order3, int w
       double* q = side ? qr : ql;
       const double r =
           learned ? double(side ? rrm : rlm)
-          : side ? double(weno<T>(w[5], w[4], w[3], w[2], w[1], wk, eps, order3, nshort))
-                 : double(weno<T>(w[0], w[1], w[2], w[3], w[4], wk, eps, order3, nshort));
+          : side ? double(weno_sel<T, CUT>(w[5], w[4], w[3], w[2], w[1], wk, eps, order3, nshort))
+                 : double(weno_sel<T, CUT>(w[0], w[1], w[2], w[3], w[4], wk, eps, order3, nshort));
       if (m == 0) {
         q[0] = bd * r;
         q[1] = (-gd) * r;
@@ -301,7 +301,7 @@ __device__ __forceinline__ int kernel_weights(int w) {
   return CUT ? W_CUTOFF : (w == W_BASIC ? W_BASIC : W_MODIFIED);
 }
 
-template <typename T, int NDIM, int D, class S>
+template <typename T, int NDIM, int D, bool CUT = false, class S>
 __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
                                           double eps, double* F, double& us,
                                           int& n3, int& n1, int& nshort,
@@ -329,7 +329,7 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
   double ql[NC], qr[NC];
   if (mr) mlp_material(Gb, Pb, mr->f6, mr->f7);
   nshort = 0;
-  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort, mr);
+  recon<T, NDIM, D, CUT>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort, mr);
   n3 = 0;
   n1 = 0;
   if (mood) {
@@ -350,7 +350,7 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
     }
     if (fail) {
       int nf3 = 0;
-      recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
+      recon<T, NDIM, D, CUT>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
 #pragma unroll
       for (int side = 0; side < 2; side++) {
         if (!(fail & (1 << side))) continue;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void face_params(const S& st, T& a, T& b, double& bd,
   }
 }
 
-template <typename T, int NDIM, int D, class S>
+template <typename T, int NDIM, int D, bool CUT = false, class S>
 __device__ __forceinline__ int face_flux_first(const S& st, int weights, double eps, double* F,
                                                double& us, int& nshort) {
   constexpr int NT = NDIM - 1, NC = 5 + NT;
@@ -414,7 +414,7 @@ __device__ __forceinline__ int face_flux_first(const S& st, int weights, double 
   face_params<T, NDIM>(st, a, b, bd, gd);
   double ql[NC], qr[NC];
   nshort = 0;
-  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort);
+  recon<T, NDIM, D, CUT>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nshort);
   const int fail = (admissible(ql[0], ql[2 + NT], ql[3 + NT], ql[4 + NT]) ? 0 : 1) |
                    (admissible(qr[0], qr[2 + NT], qr[3 + NT], qr[4 + NT]) ? 0 : 2);
   if (fail) return fail;
@@ -431,7 +431,7 @@ __device__ __forceinline__ int face_flux_first(const S& st, int weights, double 
   return 0;
 }
 
-template <typename T, int NDIM, int D, class S>
+template <typename T, int NDIM, int D, bool CUT = false, class S>
 __device__ __forceinline__ void face_flux_redo(const S& st, int fail, int weights, double eps,
                                                double* F, double& us, int& n3, int& n1) {
   constexpr int NT = NDIM - 1, NC = 5 + NT;
@@ -440,8 +440,8 @@ __device__ __forceinline__ void face_flux_redo(const S& st, int fail, int weight
   face_params<T, NDIM>(st, a, b, bd, gd);
   double ql[NC], qr[NC];
   int nsc = 0, nf3 = 0;
-  recon<T, NDIM, D>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nsc);
-  recon<T, NDIM, D>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
+  recon<T, NDIM, D, CUT>(st, 3, false, weights, T(eps), a, b, bd, gd, ql, qr, nsc);
+  recon<T, NDIM, D, CUT>(st, fail, true, weights, T(eps), a, b, bd, gd, ql, qr, nf3);
   n3 = 0;
   n1 = 0;
 #pragma unroll

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
     int n3, n1, nf;
-    face_flux<T, NDIM, D>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
+    face_flux<T, NDIM, D, CUT>(st, kernel_weights<CUT>(g.weights), g.mood, g.eps, F, us, n3, n1,
                           nf);
     // the face on a tile boundary is evaluated by both tiles; count it once
     // (in the tile to its right, or the last tile for the domain's last face)
