@@ -293,6 +293,53 @@ def test_full_size_rhs_matches_oracle(lib, ctx):
     _check(got, ref, what="rhs 1024x512")
 
 
+def test_largest_grid_rhs_is_shift_equivariant(lib, ctx):
+    """A 32768 x 16384 periodic grid (537 M cells, 25.8 GB per state; the
+    component offsets k N + cell reach 2.7e9, past 32-bit range), too large
+    for the oracle: a property that holds at any size instead.  Every face
+    is evaluated from its own six cells only, so with periodic ends the RHS
+    of a shifted state is the shifted RHS, bit for bit -- here for a shift
+    of (5, 7) cells, which moves every face to another place in its tile
+    and many faces to another tile."""
+    import torch
+    nx, ny = 32768, 16384
+    N = nx * ny
+    gen = torch.Generator(device="cuda").manual_seed(5)
+
+    def rnd(lo, hi):
+        return lo + (hi - lo) * torch.rand(N, generator=gen, device="cuda", dtype=torch.float64)
+
+    rho, p = rnd(1.0, 2.0), rnd(1e5, 2e5)
+    u, v = rnd(-50.0, 50.0), rnd(-50.0, 50.0)
+    G, P = 2.5, 0.0                      # air, gamma = 1.4
+    U = torch.empty((6, N), dtype=torch.float64, device="cuda")
+    U[0] = rho
+    U[1] = rho * u
+    U[2] = rho * v
+    U[3] = G * p + P + 0.5 * rho * (u * u + v * v)
+    U[4] = G
+    U[5] = P
+    del rho, p, u, v
+    grid = lib.make_grid((nx, ny), (1.0 / nx, 1.0 / ny), (1, 1), (1, 1))
+    opts = lib.make_opts()
+    st = lib.new_stats()
+    out1 = ctx.rhs(U, grid, opts, stats=st)
+    U2 = U.view(6, ny, nx).roll(shifts=(7, 5), dims=(1, 2)).reshape(6, N)
+    del U
+    out2 = ctx.rhs(U2, grid, opts, stats=st)
+    del U2
+    want = out1.view(6, ny, nx).roll(shifts=(7, 5), dims=(1, 2)).reshape(6, N)
+    del out1
+    torch.cuda.synchronize()
+    assert lib.read_stats(st).status == 0
+    assert bool(torch.isfinite(out2).all())
+    same = torch.equal(out2.view(torch.int64), want.view(torch.int64))
+    print(f"[parity] {nx}x{ny} periodic, shift (5, 7): bitwise={same}", flush=True)
+    del out2, want
+    torch.cuda.empty_cache()
+    assert same
+
+
 def test_full_size_2048x1024_rhs_matches_oracle(lib, ctx):
     """The 2048 x 1024 shock-bubble grid of the learned-weights workload,
     one FP64 evaluation after two steps, bit for bit."""
