@@ -1,20 +1,25 @@
 // Fused two-dimensional stage kernel of the WENO-IS finite-volume operator.
 //
 // One launch evaluates a whole Runge-Kutta stage of a 2D grid: a workgroup
-// owns a TX x TY tile of cells and
+// of 256 lanes owns a 15 x 16 tile of cells and
 //   1. loads U for the tile plus a cross-shaped halo of 3 cells on each side
 //      along x (for the tile's rows) and along y (for its columns) -- the
 //      method is dimension by dimension (Sec. 3), so no corner cell is
 //      needed -- applying each axis' boundary condition to its own halo,
 //      recovers the primitive state in FP64 (eq. (2)) and stages it in LDS;
-//   2. evaluates every x face of the tile (one lane per face: projection,
-//      WENO-IS, MOOD cascade, HLLC), then forms each cell's x terms of
-//      eqs. (5)-(6) in registers;
-//   3. evaluates every y face into the same LDS buffer, adds each cell's y
-//      terms to its x terms (the order of the dimension-by-dimension sum,
-//      L = r_x + r_y) and writes dU/dt or the Runge-Kutta stage.
+//   2. evaluates the 16 x faces of each of the 16 rows, one per lane
+//      (projection, WENO-IS, MOOD cascade, HLLC), lane = 16 row + face, so
+//      that a cell's right face sits in the next lane of the same 16-lane
+//      group: each lane forms its cell's x terms of eqs. (5)-(6) in
+//      registers from its own face and the neighbour lane's;
+//   3. evaluates the 255 y faces, writes their values over the staged rows
+//      of rho, u, v and p once every face has read those rows (the material
+//      rows Gamma and Pi, which the cells still need, are kept), adds each
+//      cell's y terms to its x terms (the order of the dimension-by-dimension
+//      sum, L = r_x + r_y) and writes dU/dt or the Runge-Kutta stage.
 // Compared with one sweep per axis, the x terms never travel through memory
-// and the state is read once per stage.
+// and the state is read once per stage; the LDS holds the staged state only
+// (22.2 KB in FP64), the y faces reusing part of it.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -25,36 +30,44 @@ namespace isw {
 
 namespace {
 
+constexpr int kTX = 15, kTY = 16, kThreads = 256;
+constexpr int kSX = kTX + 6, kSY = kTY + 6;  // staged rectangle; its corners stay unused
+constexpr int kQROW = kSX * kSY;
+
+// LDS row of primitive component c (rho, u, v, p, Gamma, Pi): the material
+// rows first, so that the y-face values can overlay the other four.
+__device__ __forceinline__ int srow(int c) { return c >= 4 ? c - 4 : c + 2; }
+
 struct LdsStencil2 {
-  const double* base;  // component 0, stencil position 0
-  int cstride, pstride;
+  const double* base;  // LDS row 0, stencil position 0
+  int pstride;
   __device__ __forceinline__ double operator()(int c, int j) const {
-    return base[c * cstride + j * pstride];
+    return base[srow(c) * kQROW + j * pstride];
   }
 };
 
 }  // namespace
 
-template <typename T, int TX, int TY, int NTHR, int MODE, bool CUT, bool GATHER>
-__global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(SweepArgs g) {
-  constexpr int NDIM = 2, NC = 6;
-  constexpr int SX = TX + 6, SY = TY + 6;  // staged rectangle; its corners stay unused
-  constexpr int QROW = SX * SY;
-  constexpr int NFX = (TX + 1) * TY;       // x faces of the tile, row-major
-  constexpr int NFY = TX * (TY + 1);       // y faces of the tile, row-major
-  constexpr int NFMAX = NFX > NFY ? NFX : NFY;
-  constexpr int NCELL = TX * TY;
-  constexpr int CPL = (NCELL + NTHR - 1) / NTHR;  // cells per lane
-  __shared__ double sq[NC * QROW];               // primitives [c][yy][xx]
-  // face fluxes and u* in the arithmetic's type (the float form's fluxes
-  // are float values, so float storage is exact); x faces, then y faces
-  __shared__ T sf[(NC + 1) * NFMAX];
+// At least 4 resident waves per SIMD (registers capped at 128): the x phase
+// holds a face's values and the neighbour lane's at once.  The cut-off
+// weights with the gathered cascade need more (about 250 in FP64) and get 2.
+template <typename T, int MODE, bool CUT, bool GATHER>
+__global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kernel(SweepArgs g) {
+  constexpr int NDIM = 2, NC = 6, TX = kTX, TY = kTY, NTHR = kThreads;
+  constexpr int SX = kSX, QROW = kQROW;
+  constexpr int NFX = (TX + 1) * TY;  // 256 x faces: lane = 16 row + face
+  constexpr int NFY = TX * (TY + 1);  // 255 y faces: face (x, fy) at fy * TX + x
+  static_assert(NFX == NTHR && NFY <= NTHR, "one face per lane in each phase");
+  static_assert((NC + 1) * NFY <= 4 * QROW, "y faces fit over the rows of rho, u, v, p");
+  __shared__ double sq[NC * QROW];  // primitives [srow(c)][yy][xx]
   __shared__ int s_status;
   __shared__ int s_skip;
   // GATHER: faces whose MOOD check failed, per phase (face index | fail
-  // bits << 16), redone by full waves after the phase's faces
-  __shared__ int s_queue[GATHER ? NFMAX : 1];
+  // bits << 16), redone by full waves after the phase's faces; the x faces
+  // redone hand their values back through sfx
+  __shared__ int s_queue[GATHER ? NTHR : 1];
   __shared__ int s_nq[GATHER ? 2 : 1];
+  __shared__ double sfx[GATHER ? (NC + 1) * NFX : 1];
 
   const int64_t nx = g.n[0], ny = g.n[1], N = nx * ny;
   // Tile order.  The hardware deals workgroups to its 8 XCDs in turn
@@ -77,6 +90,7 @@ __global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(S
   const int64_t gx0 = (pos % ntx) * TX;
   const int64_t gy0 = (cls + 8 * (prow - first)) * TY;
   const int tid = threadIdx.x;
+
   if (tid == 0) {
     if constexpr (GATHER) {
       s_nq[0] = 0;
@@ -113,15 +127,37 @@ __global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(S
       else q[2] = -q[2];
     }
 #pragma unroll
-    for (int c = 0; c < NC; c++) sq[c * QROW + e] = q[c];
+    for (int c = 0; c < NC; c++) sq[srow(c) * QROW + e] = q[c];
   }
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
 
   int my3[2] = {0, 0}, my1[2] = {0, 0}, mys[2] = {0, 0};
-
   const int wts = kernel_weights<CUT>(g.weights);
+  const double dx = g.dx[0], dy = g.dx[1];
+  auto xstencil = [&](int f) {  // x face (f % 16, f / 16)
+    LdsStencil2 st;
+    st.base = &sq[(f / 16 + 3) * SX + f % 16];
+    st.pstride = 1;
+    return st;
+  };
+  auto ystencil = [&](int f) {  // y face (f % TX, f / TX)
+    LdsStencil2 st;
+    st.base = &sq[(f / TX) * SX + f % TX + 3];
+    st.pstride = SX;
+    return st;
+  };
+  // a face on a tile boundary is evaluated by both tiles: it is counted in
+  // the tile after it (the last tile for the domain's last face)
+  auto xcounted = [&](int f) {
+    const int fx = f % 16;
+    return fx < TX || gx0 + fx == nx;
+  };
+  auto ycounted = [&](int f) {
+    const int fy = f / TX;
+    return fy < TY || gy0 + fy == ny;
+  };
   // a face whose check failed joins the phase's queue: one LDS atomic per
   // wave, slots in lane order (GATHER only)
   auto enqueue = [&](int d, int f, int fail) {
@@ -133,144 +169,114 @@ __global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(S
     base = __shfl(base, lead);
     if (fail) s_queue[base + __popcll(bal & ((1ull << lane) - 1))] = f | (fail << 16);
   };
-  auto store = [&](int f, const double* F, double us) {
-#pragma unroll
-    for (int k = 0; k < NC; k++) sf[k * NFMAX + f] = T(F[k]);
-    sf[NC * NFMAX + f] = T(us);
-  };
-  auto xstencil = [&](int f) {
-    LdsStencil2 st;
-    st.base = &sq[(f / (TX + 1) + 3) * SX + f % (TX + 1)];
-    st.cstride = QROW;
-    st.pstride = 1;
-    return st;
-  };
-  auto ystencil = [&](int f) {
-    LdsStencil2 st;
-    st.base = &sq[(f / TX) * SX + f % TX + 3];
-    st.cstride = QROW;
-    st.pstride = SX;
-    return st;
-  };
-  // a face on a tile boundary is evaluated by both tiles: it is counted in
-  // the tile after it (the last tile for the domain's last face)
-  auto xcounted = [&](int f) {
-    const int fx = f % (TX + 1);
-    return fx < TX || gx0 + fx == nx;
-  };
-  auto ycounted = [&](int f) {
-    const int fy = f / TX;
-    return fy < TY || gy0 + fy == ny;
-  };
 
-  // 2. x faces: face (fx, y) lies between cells fx-1 and fx of row y
-  if constexpr (GATHER) {
-    for (int f0 = 0; f0 < NFX; f0 += NTHR) {
-      const int f = f0 + tid;
+  // 2. x faces: lane tid holds face (cx, cy), between cells cx-1 and cx of
+  // row cy, and, for cx < 15, cell (cx, cy)
+  const int cy = tid >> 4, cx = tid & 15;
+  double rx[NC];
+  {
+    double F[NC], us = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < NC; kk++) F[kk] = 0.0;
+    const bool xvalid = gy0 + cy < ny && gx0 + cx <= nx;
+    if constexpr (GATHER) {
       int fail = 0;
-      if (f < NFX && gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx) {
-        double F[NC], us;
+      if (xvalid) {
         int nsc;
-        fail = face_flux_first<T, NDIM, 0, CUT>(xstencil(f), wts, g.eps, F, us, nsc);
-        if (xcounted(f)) mys[0] += nsc;
-        if (!fail) store(f, F, us);
+        fail = face_flux_first<T, NDIM, 0, CUT>(xstencil(tid), wts, g.eps, F, us, nsc);
+        if (xcounted(tid)) mys[0] += nsc;
       }
-      enqueue(0, f, fail);
-    }
-    __syncthreads();
-    const int nq = s_nq[0];
-    if (nq) {
-      for (int q = tid; q < nq; q += NTHR) {
-        const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
-        double F[NC], us;
-        int n3, n1;
-        face_flux_redo<T, NDIM, 0, CUT>(xstencil(f), fail, wts, g.eps, F, us, n3, n1);
-        if (xcounted(f)) {
-          my3[0] += n3;
-          my1[0] += n1;
-        }
-        store(f, F, us);
-      }
+      enqueue(0, tid, fail);
       __syncthreads();
-    }
-  } else {
-    for (int f = tid; f < NFX; f += NTHR) {
-      if (!(gy0 + f / (TX + 1) < ny && gx0 + f % (TX + 1) <= nx)) continue;
-      double F[NC], us;
+      const int nq = s_nq[0];
+      if (nq) {
+        if (tid < nq) {
+          const int f = s_queue[tid] & 0xffff, fl = s_queue[tid] >> 16;
+          double Fq[NC], uq;
+          int n3, n1;
+          face_flux_redo<T, NDIM, 0, CUT>(xstencil(f), fl, wts, g.eps, Fq, uq, n3, n1);
+          if (xcounted(f)) {
+            my3[0] += n3;
+            my1[0] += n1;
+          }
+#pragma unroll
+          for (int kk = 0; kk < NC; kk++) sfx[kk * NFX + f] = Fq[kk];
+          sfx[NC * NFX + f] = uq;
+        }
+        __syncthreads();
+        if (fail) {
+#pragma unroll
+          for (int kk = 0; kk < NC; kk++) F[kk] = sfx[kk * NFX + tid];
+          us = sfx[NC * NFX + tid];
+        }
+      }
+    } else if (xvalid) {
       int n3, n1, nsc;
-      face_flux<T, NDIM, 0, CUT>(xstencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
-      if (xcounted(f)) {
+      face_flux<T, NDIM, 0, CUT>(xstencil(tid), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+      if (xcounted(tid)) {
         my3[0] += n3;
         my1[0] += n1;
         mys[0] += nsc;
       }
-      store(f, F, us);
     }
-    __syncthreads();
-  }
-
-  // x terms of eqs. (5)-(6) per cell, kept in registers (axis order; for
-  // the x axis face order and axis order coincide)
-  const double dx = g.dx[0], dy = g.dx[1];
-  double rx[CPL][NC];
+    // the face to the right of cell cx is the next lane's (same 16-lane
+    // group); for cx = 15 there is no cell and the value goes unused
+    double Fr[NC];
 #pragma unroll
-  for (int i = 0; i < CPL; i++) {
-    const int e = tid + i * NTHR;
-    const int x = e % TX, y = e / TX;
-    if (e >= NCELL) continue;
+    for (int kk = 0; kk < NC; kk++) Fr[kk] = __shfl_down(F[kk], 1, 16);
+    const double usr = __shfl_down(us, 1, 16);
+    // x terms of eqs. (5)-(6) (for the x axis face order and axis order
+    // coincide)
 #pragma unroll
-    for (int k = 0; k < NC; k++) {
-      const int f = y * (TX + 1) + x;
-      double r = -(double(sf[k * NFMAX + f + 1]) - double(sf[k * NFMAX + f])) / dx;
-      if (k >= 4) {
-        const double phi = sq[k * QROW + (y + 3) * SX + x + 3];
-        r = r + phi * (double(sf[NC * NFMAX + f + 1]) - double(sf[NC * NFMAX + f])) / dx;
+    for (int kk = 0; kk < NC; kk++) {
+      double r = -(Fr[kk] - F[kk]) / dx;
+      if (kk >= 4) {
+        const double phi = sq[srow(kk) * QROW + (cy + 3) * SX + cx + 3];
+        r = r + phi * (usr - us) / dx;
       }
-      rx[i][k] = r;
+      rx[kk] = r;
     }
   }
-  __syncthreads();
 
-  // 3. y faces: face (x, fy) lies between cells fy-1 and fy of column x
+  // 3. y faces: lane tid < 255 holds face (tid % 15, tid / 15), between
+  // cells fy-1 and fy of its column
+  double G[NC], vs = 0.0;
+  const bool yvalid = tid < NFY && gx0 + tid % TX < nx && gy0 + tid / TX <= ny;
+  int yfail = 0;
   if constexpr (GATHER) {
-    for (int f0 = 0; f0 < NFY; f0 += NTHR) {
-      const int f = f0 + tid;
-      int fail = 0;
-      if (f < NFY && gx0 + f % TX < nx && gy0 + f / TX <= ny) {
-        double F[NC], us;
-        int nsc;
-        fail = face_flux_first<T, NDIM, 1, CUT>(ystencil(f), wts, g.eps, F, us, nsc);
-        if (ycounted(f)) mys[1] += nsc;
-        if (!fail) store(f, F, us);
-      }
-      enqueue(1, f, fail);
+    if (yvalid) {
+      int nsc;
+      yfail = face_flux_first<T, NDIM, 1, CUT>(ystencil(tid), wts, g.eps, G, vs, nsc);
+      if (ycounted(tid)) mys[1] += nsc;
     }
-    __syncthreads();
+    enqueue(1, tid, yfail);
+  } else if (yvalid) {
+    int n3, n1, nsc;
+    face_flux<T, NDIM, 1, CUT>(ystencil(tid), wts, g.mood, g.eps, G, vs, n3, n1, nsc);
+    if (ycounted(tid)) {
+      my3[1] += n3;
+      my1[1] += n1;
+      mys[1] += nsc;
+    }
+  }
+  __syncthreads();  // every face has read the staged rows (GATHER: and queued)
+  double Gq[NC], vq = 0.0;
+  int fq = -1;
+  if constexpr (GATHER) {
+    // the gathered faces, by full waves; their values go to LDS with the
+    // others, once every redo has read the staged rows
     const int nq = s_nq[1];
-    for (int q = tid; q < nq; q += NTHR) {
-      const int f = s_queue[q] & 0xffff, fail = s_queue[q] >> 16;
-      double F[NC], us;
+    if (tid < nq) {
+      fq = s_queue[tid] & 0xffff;
+      const int fl = s_queue[tid] >> 16;
       int n3, n1;
-      face_flux_redo<T, NDIM, 1, CUT>(ystencil(f), fail, wts, g.eps, F, us, n3, n1);
-      if (ycounted(f)) {
+      face_flux_redo<T, NDIM, 1, CUT>(ystencil(fq), fl, wts, g.eps, Gq, vq, n3, n1);
+      if (ycounted(fq)) {
         my3[1] += n3;
         my1[1] += n1;
       }
-      store(f, F, us);
     }
-  } else {
-    for (int f = tid; f < NFY; f += NTHR) {
-      if (!(gx0 + f % TX < nx && gy0 + f / TX <= ny)) continue;
-      double F[NC], us;
-      int n3, n1, nsc;
-      face_flux<T, NDIM, 1, CUT>(ystencil(f), wts, g.mood, g.eps, F, us, n3, n1, nsc);
-      if (ycounted(f)) {
-        my3[1] += n3;
-        my1[1] += n1;
-        mys[1] += nsc;
-      }
-      store(f, F, us);
-    }
+    if (nq) __syncthreads();
   }
   if (g.stats && g.mood) {
     const unsigned long long b = __ballot((my3[0] | my1[0] | my3[1] | my1[1]) != 0);
@@ -292,26 +298,34 @@ __global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(S
         atomicAdd(&g.shortcut[(blk & 255) * 3 + d], (unsigned long long)ws);
     }
   }
+  // y-face values over the rows of rho, u, v, p
+  double* ov = sq + 2 * QROW;
+  if (yvalid && !yfail) {
+#pragma unroll
+    for (int kk = 0; kk < NC; kk++) ov[kk * NFY + tid] = G[kk];
+    ov[NC * NFY + tid] = vs;
+  }
+  if (GATHER && fq >= 0) {
+#pragma unroll
+    for (int kk = 0; kk < NC; kk++) ov[kk * NFY + fq] = Gq[kk];
+    ov[NC * NFY + fq] = vq;
+  }
   __syncthreads();
 
   // y terms added to the x terms (face order -> axis order: u_n = v is
   // component 2, u_t = u component 1), then the output step
+  if (cx < TX && gx0 + cx < nx && gy0 + cy < ny) {
+    const int64_t cell = (gy0 + cy) * nx + gx0 + cx;
+    const int fb = cy * TX + cx, fa = fb + TX;  // the cell's lower and upper faces
 #pragma unroll
-  for (int i = 0; i < CPL; i++) {
-    const int e = tid + i * NTHR;
-    const int x = e % TX, y = e / TX;
-    if (e >= NCELL || gx0 + x >= nx || gy0 + y >= ny) continue;
-    const int64_t cell = (gy0 + y) * nx + gx0 + x;
-#pragma unroll
-    for (int k = 0; k < NC; k++) {
-      const int kc = axis_comp<NDIM, 1>(k);
-      const int f = y * TX + x;
-      double r = -(double(sf[k * NFMAX + f + TX]) - double(sf[k * NFMAX + f])) / dy;
-      if (k >= 4) {
-        const double phi = sq[kc * QROW + (y + 3) * SX + x + 3];
-        r = r + phi * (double(sf[NC * NFMAX + f + TX]) - double(sf[NC * NFMAX + f])) / dy;
+    for (int kk = 0; kk < NC; kk++) {
+      const int kc = axis_comp<NDIM, 1>(kk);
+      double r = -(ov[kk * NFY + fa] - ov[kk * NFY + fb]) / dy;
+      if (kk >= 4) {
+        const double phi = sq[srow(kc) * QROW + (cy + 3) * SX + cx + 3];
+        r = r + phi * (ov[NC * NFY + fa] - ov[NC * NFY + fb]) / dy;
       }
-      const double L = rx[i][kc] + r;
+      const double L = rx[kc] + r;
       const int64_t o = kc * N + cell;
       if (MODE == OUT_RHS) {
         g.Rout[o] = L;
@@ -329,9 +343,6 @@ __global__ __launch_bounds__(NTHR, GATHER && !CUT ? 4 : 1) void stage2d_kernel(S
   }
 }
 
-// 16 x 15 tiles: 255 x faces and 256 y faces, one per lane in each phase.
-constexpr int kTX = 16, kTY = 15, kThreads = 256;
-
 template <typename T, int MODE, bool CUT, bool GATHER>
 static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   // one workgroup per tile: the kernel maps block b to tile (b & 7, b >> 3)
@@ -342,10 +353,10 @@ static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(kThreads);
   if (ev.start)
-    hipExtLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT, GATHER>), grid, block, 0, s,
-                          ev.start, ev.stop, 0, a);
+    hipExtLaunchKernelGGL((stage2d_kernel<T, MODE, CUT, GATHER>), grid, block, 0, s, ev.start,
+                          ev.stop, 0, a);
   else
-    hipLaunchKernelGGL((stage2d_kernel<T, kTX, kTY, kThreads, MODE, CUT, GATHER>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((stage2d_kernel<T, MODE, CUT, GATHER>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
