@@ -202,7 +202,7 @@ ISWENO_API int isweno_rk3_step(isweno_ctx *ctx, const isweno_grid *grid,
 /* isweno_rk3_step for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same step with the same results, but its intermediate states and
- * time-step word live in a fixed scratch array of the library (a device
+ * time-step words live in a fixed scratch array of the library (a device
  * global of 128 MiB plus 256 bytes that every GPU the library runs on holds
  * until the process ends) instead of the context's workspace, and it
  * launches its kernels directly (no graph, no timing events).  It calls no

@@ -181,7 +181,7 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
 
 // One RK3 step on stream s: the time step (when cfl > 0), then the three
 // stages, with the intermediate states in U1 and U2 (nc*N each) and the
-// time-step reduction word maxbits (zero on entry, left zero).
+// time-step reduction words maxbits (two, zero on entry, left zero).
 hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
                        double* dt, isweno_stats* stats, double* U1, double* U2,
                        unsigned long long* maxbits, bool timed, hipStream_t s) {
@@ -218,14 +218,14 @@ hipError_t enqueue_rk3_ws(isweno_ctx* c, const isweno_grid* g, const isweno_opts
 
 // ---------------------------------------------------------------------------
 // Scratch of the allocation-free step (isweno_rk3_step_noalloc): the
-// time-step reduction word in its first 256 bytes, then U1 and U2.  A device
+// time-step reduction words in its first kCflWordsBytes, then U1 and U2.  A device
 // global: every GPU the library runs on holds its own copy from the load of
 // the library's code object until the process ends.  Host code never uses
 // the array's name as an address: scratch_addr() returns this device's copy,
 // looked up once per device with hipGetSymbolAddress.
 // ---------------------------------------------------------------------------
 constexpr size_t kScratchStates = (size_t)128 << 20;  // bytes for U1 and U2
-static __device__ __align__(256) unsigned char scratch[256 + kScratchStates];
+static __device__ __align__(256) unsigned char scratch[isw::kCflWordsBytes + kScratchStates];
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -281,8 +281,8 @@ int isweno_create(isweno_ctx** out, int device) {
     delete c;
     return ISWENO_ERR_DEVICE;
   }
-  if (hipMalloc(&c->maxbits, 256) != hipSuccess ||
-      hipMemset(c->maxbits, 0, 256) != hipSuccess ||
+  if (hipMalloc(&c->maxbits, isw::kCflWordsBytes) != hipSuccess ||
+      hipMemset(c->maxbits, 0, isw::kCflWordsBytes) != hipSuccess ||
       hipMalloc(&c->shortcut, kShortcutBytes) != hipSuccess ||
       hipMemset(c->shortcut, 0, kShortcutBytes) != hipSuccess) {
     if (c->maxbits) (void)hipFree(c->maxbits);
@@ -417,11 +417,11 @@ int isweno_rk3_step_noalloc(isweno_ctx* c, const isweno_grid* g, const isweno_op
   if (!base) return ISWENO_ERR_DEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto* maxbits = reinterpret_cast<unsigned long long*>(base);
-  double* U1 = reinterpret_cast<double*>(base + 256);
+  double* U1 = reinterpret_cast<double*>(base + isw::kCflWordsBytes);
   double* U2 = U1 + (size_t)nc * (size_t)N;
-  // the reduction word keeps whatever the previous call on this GPU left:
-  // clear it with a kernel (no memset node, should a caller capture this)
-  if (o->cfl > 0.0 && isw::launch_zero_u64(maxbits, s) != hipSuccess) return ISWENO_ERR_DEVICE;
+  // the reduction words keep whatever the previous call on this GPU left:
+  // clear them with a kernel (no memset node, should a caller capture this)
+  if (o->cfl > 0.0 && isw::launch_zero_cfl(maxbits, s) != hipSuccess) return ISWENO_ERR_DEVICE;
   return enqueue_rk3(c, g, o, U, dt, stats, U1, U2, maxbits, false, s) == hipSuccess
              ? ISWENO_OK
              : ISWENO_ERR_DEVICE;

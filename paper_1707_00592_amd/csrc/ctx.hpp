@@ -15,7 +15,7 @@ struct isweno_ctx {
   int ncu = 256;
   double* ws = nullptr;          // two state-sized buffers (U1, U2)
   size_t ws_bytes = 0;
-  unsigned long long* maxbits = nullptr;  // time-step reduction word
+  unsigned long long* maxbits = nullptr;  // time-step reduction words (max, ticket)
   unsigned long long* shortcut = nullptr;  // 256 x 3 reconstruction-shortcut counters (timing only)
   float* mlp_part = nullptr;     // per-workgroup partial gradients of isweno_mlp_loss_grad
   int mlp_part_blocks = 0;

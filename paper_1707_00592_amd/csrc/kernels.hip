@@ -9,59 +9,69 @@
 namespace isw {
 
 // ---------------------------------------------------------------------------
-// Time step: per-cell sum_d (|u_d| + c)/dx_d, block max, then a device-wide
-// max through an integer atomic on the (positive) double's bits.
+// Time step in one launch: per-cell sum_d (|u_d| + c)/dx_d, the workgroup's
+// max, a device-wide max through an integer atomic on the bits of the
+// (positive) doubles, which order as the doubles do (a NaN above every
+// number), and dt formed by the workgroup that finishes last, found by a
+// ticket counter.  words[kCflMax] and words[kCflTicket] start zero and are
+// left zero.
 // ---------------------------------------------------------------------------
+constexpr int kCflThreads = 1024;
+constexpr int kCflCells = 2;  // cells per lane and pass, loaded before any arithmetic
+
 template <int NDIM>
-__global__ __launch_bounds__(256) void cfl_reduce_kernel(
-    const double* U, int64_t n0, int64_t n1, int64_t n2, double dx0,
-    double dx1, double dx2, unsigned long long* maxbits) {
+__global__ __launch_bounds__(kCflThreads) void cfl_kernel(
+    const double* U, int64_t n0, int64_t n1, int64_t n2, double dx0, double dx1, double dx2,
+    double cfl, double dt_max, unsigned long long* words, double* dt) {
   constexpr int NC = 4 + NDIM;
-  constexpr int UNR = 4;  // cells per lane and pass, loaded before any arithmetic
   const int64_t N = n0 * n1 * n2;
   const double dxs[3] = {dx0, dx1, dx2};
   double m = 0.0;
-  const int64_t span = (int64_t)blockDim.x * UNR;
+  const int64_t span = (int64_t)kCflThreads * kCflCells;
   for (int64_t c0 = blockIdx.x * span + threadIdx.x; c0 < N; c0 += (int64_t)gridDim.x * span) {
-    double u[UNR][NC];
+    double u[kCflCells][NC];
 #pragma unroll
-    for (int r = 0; r < UNR; r++) {
-      const int64_t c = c0 + (int64_t)r * blockDim.x;
+    for (int r = 0; r < kCflCells; r++) {
+      const int64_t c = c0 + (int64_t)r * kCflThreads;
 #pragma unroll
       for (int k = 0; k < NC; k++) u[r][k] = c < N ? U[k * N + c] : 1.0;
     }
 #pragma unroll
-    for (int r = 0; r < UNR; r++) {
-      if (c0 + (int64_t)r * blockDim.x >= N) continue;
+    for (int r = 0; r < kCflCells; r++) {
+      if (c0 + (int64_t)r * kCflThreads >= N) continue;
       double q[NC];
       cons_prim<NDIM>(u[r], q);
       const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
-      double s = (fabs(q[1]) + cs) / dxs[0];
+      double sp = (fabs(q[1]) + cs) / dxs[0];
 #pragma unroll
-      for (int a = 1; a < NDIM; a++) s = s + (fabs(q[1 + a]) + cs) / dxs[a];
-      m = (s > m || s != s) ? s : m;
+      for (int a = 1; a < NDIM; a++) sp = sp + (fabs(q[1 + a]) + cs) / dxs[a];
+      m = (sp > m || sp != sp) ? sp : m;
     }
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = m;
+  unsigned long long b = (unsigned long long)__double_as_longlong(m);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(b, o);
+    b = x > b ? x : b;
+  }
+  __shared__ unsigned long long red[kCflThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const double x = red[threadIdx.x + o];
-      if (x > red[threadIdx.x] || x != x) red[threadIdx.x] = x;
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kCflThreads / 64; w++) b = red[w] > b ? red[w] : b;
+    atomicMax(&words[kCflMax], b);
+    __threadfence();
+    if (atomicAdd(&words[kCflTicket], 1ull) == gridDim.x - 1) {
+      // every other workgroup's max precedes its ticket
+      __threadfence();
+      const double mx = __longlong_as_double((long long)atomicMax(&words[kCflMax], 0ull));
+      double h = cfl / mx;
+      if (dt_max > 0.0 && h > dt_max) h = dt_max;
+      *dt = h;
+      atomicExch(&words[kCflMax], 0ull);
+      atomicExch(&words[kCflTicket], 0ull);
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(red[0]));
-}
-
-__global__ void cfl_finalize_kernel(unsigned long long* maxbits, double cfl,
-                                    double dt_max, double* dt) {
-  const double m = __longlong_as_double((long long)*maxbits);
-  double h = cfl / m;
-  if (dt_max > 0.0 && h > dt_max) h = dt_max;
-  *dt = h;
-  *maxbits = 0ull;
 }
 
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,
@@ -78,49 +88,41 @@ hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int 
                         : launch_sweep_p<double, false, false>(ndim, D, a, mode, readR, s, ev);
 }
 
-__global__ void zero_u64_kernel(unsigned long long* w) { *w = 0ull; }
+__global__ void zero_cfl_kernel(unsigned long long* w) {
+  w[kCflMax] = 0ull;
+  w[kCflTicket] = 0ull;
+}
 
-hipError_t launch_zero_u64(unsigned long long* w, hipStream_t s) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w);
+hipError_t launch_zero_cfl(unsigned long long* w, hipStream_t s) {
+  hipLaunchKernelGGL(zero_cfl_kernel, dim3(1), dim3(1), 0, s, w);
   return hipGetLastError();
 }
 
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
-                      double cfl, double dt_max, unsigned long long* maxbits, double* dt,
+                      double cfl, double dt_max, unsigned long long* words, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev) {
   if (n[0] < 1 || n[1] < 1 || n[2] < 1 || ncu < 1) return hipErrorInvalidValue;
   const int64_t N = n[0] * n[1] * n[2];
-  int64_t blocks = (N + 1023) / 1024;
-  // one workgroup per CU: every workgroup ends in one atomic on the same
-  // word, and those serialise (measured: the kernel time grows by about
-  // 10 ns per workgroup)
-  const int64_t cap = (int64_t)ncu;
-  if (blocks > cap) blocks = cap;
+  int64_t blocks = (N + kCflThreads * kCflCells - 1) / (kCflThreads * kCflCells);
+  // one workgroup per CU at most: every workgroup ends in atomics on the
+  // same two words
+  if (blocks > (int64_t)ncu) blocks = ncu;
   if (blocks < 1) blocks = 1;
-  // events (timing only, never captured): start of the reduction, end of
-  // the finalisation
-  const dim3 grid((unsigned)blocks), block(256);
-  auto reduce = [&](auto kern) {
+  const dim3 grid((unsigned)blocks), block(kCflThreads);
+  auto go = [&](auto kern) {
     if (ev.start)
-      hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev.start, nullptr, 0, U, n[0], n[1], n[2],
-                            dx[0], dx[1], dx[2], maxbits);
+      hipExtLaunchKernelGGL(kern, grid, block, 0, s, ev.start, ev.stop, 0, U, n[0], n[1], n[2],
+                            dx[0], dx[1], dx[2], cfl, dt_max, words, dt);
     else
-      hipLaunchKernelGGL(kern, grid, block, 0, s, U, n[0], n[1], n[2], dx[0], dx[1], dx[2],
-                         maxbits);
+      hipLaunchKernelGGL(kern, grid, block, 0, s, U, n[0], n[1], n[2], dx[0], dx[1], dx[2], cfl,
+                         dt_max, words, dt);
   };
   if (ndim == 1)
-    reduce(cfl_reduce_kernel<1>);
+    go(cfl_kernel<1>);
   else if (ndim == 2)
-    reduce(cfl_reduce_kernel<2>);
+    go(cfl_kernel<2>);
   else
-    reduce(cfl_reduce_kernel<3>);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (ev.stop)
-    hipExtLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, nullptr, ev.stop, 0,
-                          maxbits, cfl, dt_max, dt);
-  else
-    hipLaunchKernelGGL(cfl_finalize_kernel, dim3(1), dim3(1), 0, s, maxbits, cfl, dt_max, dt);
+    go(cfl_kernel<3>);
   return hipGetLastError();
 }
 

@@ -30,14 +30,18 @@ hipError_t launch_sweep_cut(int precision, int ndim, int D, const SweepArgs& a, 
 hipError_t launch_stage2d(int precision, const SweepArgs& a, int mode, hipStream_t s,
                           LaunchEvents ev = {});
 
-// dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0); maxbits is
-// a zeroed device word, left zeroed on exit.
+// Device words of the time-step reduction (64-bit): the max, the ticket.
+constexpr int kCflMax = 0, kCflTicket = 1;
+constexpr size_t kCflWordsBytes = 256;
+
+// dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0), one launch;
+// the words (kCflWordsBytes) are zero on entry and left zero.
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
-                      double cfl, double dt_max, unsigned long long* maxbits, double* dt,
+                      double cfl, double dt_max, unsigned long long* words, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev = {});
 
-// *w = 0 by a one-lane kernel (used instead of a memset, which a captured
-// graph should not contain).
-hipError_t launch_zero_u64(unsigned long long* w, hipStream_t s);
+// Zeroes the time-step words by a kernel (used instead of a
+// memset, which a captured graph should not contain).
+hipError_t launch_zero_cfl(unsigned long long* w, hipStream_t s);
 
 }  // namespace isw
