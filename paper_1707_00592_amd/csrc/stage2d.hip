@@ -7,19 +7,17 @@
 //      method is dimension by dimension (Sec. 3), so no corner cell is
 //      needed -- applying each axis' boundary condition to its own halo,
 //      recovers the primitive state in FP64 (eq. (2)) and stages it in LDS;
-//   2. evaluates the 16 x faces of each of the 16 rows, one per lane
-//      (projection, WENO-IS, MOOD cascade, HLLC), lane = 16 row + face, so
-//      that a cell's right face sits in the next lane of the same 16-lane
-//      group: each lane forms its cell's x terms of eqs. (5)-(6) in
-//      registers from its own face and the neighbour lane's;
-//   3. evaluates the 255 y faces, writes their values over the staged rows
-//      of rho, u, v and p once every face has read those rows (the material
-//      rows Gamma and Pi, which the cells still need, are kept), adds each
-//      cell's y terms to its x terms (the order of the dimension-by-dimension
+//   2. evaluates the 255 y faces (projection, WENO-IS, MOOD cascade, HLLC),
+//      one per lane, into an LDS face buffer;
+//   3. evaluates the 16 x faces of each of the 16 rows, one per lane,
+//      lane = 16 row + face, so that a cell's right face sits in the next
+//      lane of the same 16-lane group: each lane forms its cell's x terms of
+//      eqs. (5)-(6) from its own face and the neighbour lane's, adds the y
+//      terms from the face buffer (the order of the dimension-by-dimension
 //      sum, L = r_x + r_y) and writes dU/dt or the Runge-Kutta stage.
-// Compared with one sweep per axis, the x terms never travel through memory
-// and the state is read once per stage; the LDS holds the staged state only
-// (22.2 KB in FP64), the y faces reusing part of it.
+// Compared with one sweep per axis, neither axis' terms travel through
+// memory and the state is read once per stage; no face evaluation runs with
+// another face's results held in registers.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -34,23 +32,19 @@ constexpr int kTX = 15, kTY = 16, kThreads = 256;
 constexpr int kSX = kTX + 6, kSY = kTY + 6;  // staged rectangle; its corners stay unused
 constexpr int kQROW = kSX * kSY;
 
-// LDS row of primitive component c (rho, u, v, p, Gamma, Pi): the material
-// rows first, so that the y-face values can overlay the other four.
-__device__ __forceinline__ int srow(int c) { return c >= 4 ? c - 4 : c + 2; }
-
 struct LdsStencil2 {
-  const double* base;  // LDS row 0, stencil position 0
+  const double* base;  // LDS row of component 0, stencil position 0
   int pstride;
   __device__ __forceinline__ double operator()(int c, int j) const {
-    return base[srow(c) * kQROW + j * pstride];
+    return base[c * kQROW + j * pstride];
   }
 };
 
 }  // namespace
 
-// At least 4 resident waves per SIMD (registers capped at 128): the x phase
-// holds a face's values and the neighbour lane's at once.  The cut-off
-// weights with the gathered cascade need more (about 250 in FP64) and get 2.
+// At least 4 resident waves per SIMD (registers capped at 128).  The
+// cut-off weights with the gathered cascade need more (about 250 in FP64)
+// and get 2.
 template <typename T, int MODE, bool CUT, bool GATHER>
 __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kernel(SweepArgs g) {
   constexpr int NDIM = 2, NC = 6, TX = kTX, TY = kTY, NTHR = kThreads;
@@ -58,8 +52,10 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   constexpr int NFX = (TX + 1) * TY;  // 256 x faces: lane = 16 row + face
   constexpr int NFY = TX * (TY + 1);  // 255 y faces: face (x, fy) at fy * TX + x
   static_assert(NFX == NTHR && NFY <= NTHR, "one face per lane in each phase");
-  static_assert((NC + 1) * NFY <= 4 * QROW, "y faces fit over the rows of rho, u, v, p");
-  __shared__ double sq[NC * QROW];  // primitives [srow(c)][yy][xx]
+  __shared__ double sq[NC * QROW];  // primitives [c][yy][xx]
+  // y-face fluxes and v* in the arithmetic's type (the float form's fluxes
+  // are float values, so float storage is exact)
+  __shared__ T sfy[(NC + 1) * NFY];
   __shared__ int s_status;
   __shared__ int s_skip;
   // GATHER: faces whose MOOD check failed, per phase (face index | fail
@@ -67,7 +63,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   // redone hand their values back through sfx
   __shared__ int s_queue[GATHER ? NTHR : 1];
   __shared__ int s_nq[GATHER ? 2 : 1];
-  __shared__ double sfx[GATHER ? (NC + 1) * NFX : 1];
+  __shared__ T sfx[GATHER ? (NC + 1) * NFX : 1];
 
   const int64_t nx = g.n[0], ny = g.n[1], N = nx * ny;
   // Tile order.  The hardware deals workgroups to its 8 XCDs in turn
@@ -127,7 +123,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
       else q[2] = -q[2];
     }
 #pragma unroll
-    for (int c = 0; c < NC; c++) sq[srow(c) * QROW + e] = q[c];
+    for (int c = 0; c < NC; c++) sq[c * QROW + e] = q[c];
   }
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
@@ -147,6 +143,11 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     st.base = &sq[(f / TX) * SX + f % TX + 3];
     st.pstride = SX;
     return st;
+  };
+  auto storey = [&](int f, const double* G, double vs) {
+#pragma unroll
+    for (int kk = 0; kk < NC; kk++) sfy[kk * NFY + f] = T(G[kk]);
+    sfy[NC * NFY + f] = T(vs);
   };
   // a face on a tile boundary is evaluated by both tiles: it is counted in
   // the tile after it (the last tile for the domain's last face)
@@ -170,113 +171,94 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     if (fail) s_queue[base + __popcll(bal & ((1ull << lane) - 1))] = f | (fail << 16);
   };
 
-  // 2. x faces: lane tid holds face (cx, cy), between cells cx-1 and cx of
-  // row cy, and, for cx < 15, cell (cx, cy)
-  const int cy = tid >> 4, cx = tid & 15;
-  double rx[NC];
+  // 2. y faces: lane tid < 255 holds face (tid % 15, tid / 15), between
+  // cells fy-1 and fy of its column
   {
-    double F[NC], us = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < NC; kk++) F[kk] = 0.0;
-    const bool xvalid = gy0 + cy < ny && gx0 + cx <= nx;
+    const bool yvalid = tid < NFY && gx0 + tid % TX < nx && gy0 + tid / TX <= ny;
     if constexpr (GATHER) {
       int fail = 0;
-      if (xvalid) {
+      if (yvalid) {
+        double G[NC], vs;
         int nsc;
-        fail = face_flux_first<T, NDIM, 0, CUT>(xstencil(tid), wts, g.eps, F, us, nsc);
-        if (xcounted(tid)) mys[0] += nsc;
+        fail = face_flux_first<T, NDIM, 1, CUT>(ystencil(tid), wts, g.eps, G, vs, nsc);
+        if (ycounted(tid)) mys[1] += nsc;
+        if (!fail) storey(tid, G, vs);
       }
-      enqueue(0, tid, fail);
+      enqueue(1, tid, fail);
       __syncthreads();
-      const int nq = s_nq[0];
-      if (nq) {
-        if (tid < nq) {
-          const int f = s_queue[tid] & 0xffff, fl = s_queue[tid] >> 16;
-          double Fq[NC], uq;
-          int n3, n1;
-          face_flux_redo<T, NDIM, 0, CUT>(xstencil(f), fl, wts, g.eps, Fq, uq, n3, n1);
-          if (xcounted(f)) {
-            my3[0] += n3;
-            my1[0] += n1;
-          }
-#pragma unroll
-          for (int kk = 0; kk < NC; kk++) sfx[kk * NFX + f] = Fq[kk];
-          sfx[NC * NFX + f] = uq;
+      // the gathered faces, by full waves
+      const int nq = s_nq[1];
+      if (tid < nq) {
+        const int f = s_queue[tid] & 0xffff, fl = s_queue[tid] >> 16;
+        double G[NC], vs;
+        int n3, n1;
+        face_flux_redo<T, NDIM, 1, CUT>(ystencil(f), fl, wts, g.eps, G, vs, n3, n1);
+        if (ycounted(f)) {
+          my3[1] += n3;
+          my1[1] += n1;
         }
-        __syncthreads();
-        if (fail) {
-#pragma unroll
-          for (int kk = 0; kk < NC; kk++) F[kk] = sfx[kk * NFX + tid];
-          us = sfx[NC * NFX + tid];
-        }
+        storey(f, G, vs);
       }
-    } else if (xvalid) {
+    } else if (yvalid) {
+      double G[NC], vs;
       int n3, n1, nsc;
-      face_flux<T, NDIM, 0, CUT>(xstencil(tid), wts, g.mood, g.eps, F, us, n3, n1, nsc);
-      if (xcounted(tid)) {
-        my3[0] += n3;
-        my1[0] += n1;
-        mys[0] += nsc;
-      }
-    }
-    // the face to the right of cell cx is the next lane's (same 16-lane
-    // group); for cx = 15 there is no cell and the value goes unused
-    double Fr[NC];
-#pragma unroll
-    for (int kk = 0; kk < NC; kk++) Fr[kk] = __shfl_down(F[kk], 1, 16);
-    const double usr = __shfl_down(us, 1, 16);
-    // x terms of eqs. (5)-(6) (for the x axis face order and axis order
-    // coincide)
-#pragma unroll
-    for (int kk = 0; kk < NC; kk++) {
-      double r = -(Fr[kk] - F[kk]) / dx;
-      if (kk >= 4) {
-        const double phi = sq[srow(kk) * QROW + (cy + 3) * SX + cx + 3];
-        r = r + phi * (usr - us) / dx;
-      }
-      rx[kk] = r;
-    }
-  }
-
-  // 3. y faces: lane tid < 255 holds face (tid % 15, tid / 15), between
-  // cells fy-1 and fy of its column
-  double G[NC], vs = 0.0;
-  const bool yvalid = tid < NFY && gx0 + tid % TX < nx && gy0 + tid / TX <= ny;
-  int yfail = 0;
-  if constexpr (GATHER) {
-    if (yvalid) {
-      int nsc;
-      yfail = face_flux_first<T, NDIM, 1, CUT>(ystencil(tid), wts, g.eps, G, vs, nsc);
-      if (ycounted(tid)) mys[1] += nsc;
-    }
-    enqueue(1, tid, yfail);
-  } else if (yvalid) {
-    int n3, n1, nsc;
-    face_flux<T, NDIM, 1, CUT>(ystencil(tid), wts, g.mood, g.eps, G, vs, n3, n1, nsc);
-    if (ycounted(tid)) {
-      my3[1] += n3;
-      my1[1] += n1;
-      mys[1] += nsc;
-    }
-  }
-  __syncthreads();  // every face has read the staged rows (GATHER: and queued)
-  double Gq[NC], vq = 0.0;
-  int fq = -1;
-  if constexpr (GATHER) {
-    // the gathered faces, by full waves; their values go to LDS with the
-    // others, once every redo has read the staged rows
-    const int nq = s_nq[1];
-    if (tid < nq) {
-      fq = s_queue[tid] & 0xffff;
-      const int fl = s_queue[tid] >> 16;
-      int n3, n1;
-      face_flux_redo<T, NDIM, 1, CUT>(ystencil(fq), fl, wts, g.eps, Gq, vq, n3, n1);
-      if (ycounted(fq)) {
+      face_flux<T, NDIM, 1, CUT>(ystencil(tid), wts, g.mood, g.eps, G, vs, n3, n1, nsc);
+      if (ycounted(tid)) {
         my3[1] += n3;
         my1[1] += n1;
+        mys[1] += nsc;
+      }
+      storey(tid, G, vs);
+    }
+  }
+  __syncthreads();
+
+  // 3. x faces: lane tid holds face (cx, cy), between cells cx-1 and cx of
+  // row cy, and, for cx < 15, cell (cx, cy)
+  const int cy = tid >> 4, cx = tid & 15;
+  double F[NC], us = 0.0;
+#pragma unroll
+  for (int kk = 0; kk < NC; kk++) F[kk] = 0.0;
+  const bool xvalid = gy0 + cy < ny && gx0 + cx <= nx;
+  if constexpr (GATHER) {
+    int fail = 0;
+    if (xvalid) {
+      int nsc;
+      fail = face_flux_first<T, NDIM, 0, CUT>(xstencil(tid), wts, g.eps, F, us, nsc);
+      if (xcounted(tid)) mys[0] += nsc;
+    }
+    enqueue(0, tid, fail);
+    __syncthreads();
+    const int nq = s_nq[0];
+    if (nq) {
+      if (tid < nq) {
+        const int f = s_queue[tid] & 0xffff, fl = s_queue[tid] >> 16;
+        double Fq[NC], uq;
+        int n3, n1;
+        face_flux_redo<T, NDIM, 0, CUT>(xstencil(f), fl, wts, g.eps, Fq, uq, n3, n1);
+        if (xcounted(f)) {
+          my3[0] += n3;
+          my1[0] += n1;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NC; kk++) sfx[kk * NFX + f] = T(Fq[kk]);
+        sfx[NC * NFX + f] = T(uq);
+      }
+      __syncthreads();
+      if (fail) {
+#pragma unroll
+        for (int kk = 0; kk < NC; kk++) F[kk] = double(sfx[kk * NFX + tid]);
+        us = double(sfx[NC * NFX + tid]);
       }
     }
-    if (nq) __syncthreads();
+  } else if (xvalid) {
+    int n3, n1, nsc;
+    face_flux<T, NDIM, 0, CUT>(xstencil(tid), wts, g.mood, g.eps, F, us, n3, n1, nsc);
+    if (xcounted(tid)) {
+      my3[0] += n3;
+      my1[0] += n1;
+      mys[0] += nsc;
+    }
   }
   if (g.stats && g.mood) {
     const unsigned long long b = __ballot((my3[0] | my1[0] | my3[1] | my1[1]) != 0);
@@ -298,32 +280,36 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
         atomicAdd(&g.shortcut[(blk & 255) * 3 + d], (unsigned long long)ws);
     }
   }
-  // y-face values over the rows of rho, u, v, p
-  double* ov = sq + 2 * QROW;
-  if (yvalid && !yfail) {
+  // the face to the right of cell cx is the next lane's (same 16-lane
+  // group); for cx = 15 there is no cell and the value goes unused
+  double Fr[NC];
 #pragma unroll
-    for (int kk = 0; kk < NC; kk++) ov[kk * NFY + tid] = G[kk];
-    ov[NC * NFY + tid] = vs;
-  }
-  if (GATHER && fq >= 0) {
-#pragma unroll
-    for (int kk = 0; kk < NC; kk++) ov[kk * NFY + fq] = Gq[kk];
-    ov[NC * NFY + fq] = vq;
-  }
-  __syncthreads();
+  for (int kk = 0; kk < NC; kk++) Fr[kk] = __shfl_down(F[kk], 1, 16);
+  const double usr = __shfl_down(us, 1, 16);
 
-  // y terms added to the x terms (face order -> axis order: u_n = v is
+  // x terms of eqs. (5)-(6) (for the x axis face order and axis order
+  // coincide), plus the y terms (face order -> axis order: u_n = v is
   // component 2, u_t = u component 1), then the output step
   if (cx < TX && gx0 + cx < nx && gy0 + cy < ny) {
     const int64_t cell = (gy0 + cy) * nx + gx0 + cx;
-    const int fb = cy * TX + cx, fa = fb + TX;  // the cell's lower and upper faces
+    const int fb = cy * TX + cx, fa = fb + TX;  // the cell's lower and upper y faces
+    double rx[NC];
+#pragma unroll
+    for (int kk = 0; kk < NC; kk++) {
+      double r = -(Fr[kk] - F[kk]) / dx;
+      if (kk >= 4) {
+        const double phi = sq[kk * QROW + (cy + 3) * SX + cx + 3];
+        r = r + phi * (usr - us) / dx;
+      }
+      rx[kk] = r;
+    }
 #pragma unroll
     for (int kk = 0; kk < NC; kk++) {
       const int kc = axis_comp<NDIM, 1>(kk);
-      double r = -(ov[kk * NFY + fa] - ov[kk * NFY + fb]) / dy;
+      double r = -(double(sfy[kk * NFY + fa]) - double(sfy[kk * NFY + fb])) / dy;
       if (kk >= 4) {
-        const double phi = sq[srow(kc) * QROW + (cy + 3) * SX + cx + 3];
-        r = r + phi * (ov[NC * NFY + fa] - ov[NC * NFY + fb]) / dy;
+        const double phi = sq[kc * QROW + (cy + 3) * SX + cx + 3];
+        r = r + phi * (double(sfy[NC * NFY + fa]) - double(sfy[NC * NFY + fb])) / dy;
       }
       const double L = rx[kc] + r;
       const int64_t o = kc * N + cell;
