@@ -75,7 +75,7 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       bool flip;
       const int64_t li = bc_index(l, n, g.bc_lo, g.bc_hi, flip);
       double q[NC];
-      cell_prim<1>(g.Uin, total, lo + li, q);
+      cell_prim<1, T>(g.Uin, total, lo + li, q);
       if (p >= 3 && p < 3 + len) bad = bad || !cell_ok<1>(g.Uin, total, lo + li, q);
       if (flip) q[1] = -q[1];
 #pragma unroll
@@ -103,14 +103,14 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       sf[NC * NF + j] = us;
     }
     __syncthreads();
-    const double dx = g.dx[prob];
+    const Div64<T> bydx(g.dx[prob]);
     const double h = g.dt[prob];
     for (int j = tid; j < len; j += NTHR) {
       const int64_t cell = lo + l0 + j;
 #pragma unroll
       for (int k = 0; k < NC; k++) {
-        double r = -(sf[k * NF + j + 1] - sf[k * NF + j]) / dx;
-        if (k >= 3) r = r + sq[k * NP + j + 3] * (sf[NC * NF + j + 1] - sf[NC * NF + j]) / dx;
+        double r = bydx(-(sf[k * NF + j + 1] - sf[k * NF + j]));
+        if (k >= 3) r = r + bydx(sq[k * NP + j + 3] * (sf[NC * NF + j + 1] - sf[NC * NF + j]));
         const int64_t o = k * total + cell;
         if (MODE == OUT_RK1) {
           g.Uout[o] = g.U0[o] + h * r;

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     if (yhalo) iy = bc_index(gyl, ny, g.bcl[1], g.bch[1], flip);
     const int64_t cell = iy * nx + ix;
     double q[NC];
-    cell_prim<NDIM>(g.Uin, N, cell, q);
+    cell_prim<NDIM, T>(g.Uin, N, cell, q);
     if (colin && rowin) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
     if (flip) {
       if (xhalo) q[1] = -q[1];
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
 
   int my3[2] = {0, 0}, my1[2] = {0, 0}, mys[2] = {0, 0};
   const int wts = kernel_weights<CUT>(g.weights);
-  const double dx = g.dx[0], dy = g.dx[1];
+  const Div64<T> bydx(g.dx[0]), bydy(g.dx[1]);
   auto xstencil = [&](int f) {  // x face (f % 16, f / 16)
     LdsStencil2 st;
     st.base = &sq[(f / 16 + 3) * SX + f % 16];
@@ -296,20 +296,20 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     double rx[NC];
 #pragma unroll
     for (int kk = 0; kk < NC; kk++) {
-      double r = -(Fr[kk] - F[kk]) / dx;
+      double r = bydx(-(Fr[kk] - F[kk]));
       if (kk >= 4) {
         const double phi = sq[kk * QROW + (cy + 3) * SX + cx + 3];
-        r = r + phi * (usr - us) / dx;
+        r = r + bydx(phi * (usr - us));
       }
       rx[kk] = r;
     }
 #pragma unroll
     for (int kk = 0; kk < NC; kk++) {
       const int kc = axis_comp<NDIM, 1>(kk);
-      double r = -(double(sfy[kk * NFY + fa]) - double(sfy[kk * NFY + fb])) / dy;
+      double r = bydy(-(double(sfy[kk * NFY + fa]) - double(sfy[kk * NFY + fb])));
       if (kk >= 4) {
         const double phi = sq[kc * QROW + (cy + 3) * SX + cx + 3];
-        r = r + phi * (double(sfy[NC * NFY + fa]) - double(sfy[NC * NFY + fb])) / dy;
+        r = r + bydy(phi * (double(sfy[NC * NFY + fa]) - double(sfy[NC * NFY + fb])));
       }
       const double L = rx[kc] + r;
       const int64_t o = kc * N + cell;

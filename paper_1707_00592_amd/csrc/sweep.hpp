@@ -89,14 +89,38 @@ __device__ __forceinline__ int64_t bc_index(int64_t l, int64_t n, int bclo,
   return l;
 }
 
+// FP64 quotients in the kernels: exact (IEEE) in the FP64 form, which
+// reproduces the oracle bit for bit; in the float form, whose reconstruction
+// and flux are float, x times the refined reciprocal of the divisor (within
+// 2 ulp of the quotient for a normal divisor), a third of the instructions.
+template <typename T>
+__device__ __forceinline__ double div64(double x, double y) {
+  if constexpr (sizeof(T) == 8) return x / y;
+  else return x * recip(y).r;
+}
+
+// The same for many quotients by one divisor (the reciprocal formed once).
+template <typename T>
+struct Div64 {
+  double y, r;
+  __device__ __forceinline__ explicit Div64(double d) : y(d), r(0.0) {
+    if constexpr (sizeof(T) == 4) r = recip(d).r;
+  }
+  __device__ __forceinline__ double operator()(double x) const {
+    if constexpr (sizeof(T) == 8) return x / y;
+    else return x * r;
+  }
+};
+
 // Primitive recovery of one cell, axis order (rho, u_x.., p, Gamma, Pi),
-// eq. (2): p = (E - rho |u|^2 / 2 - Pi) / Gamma.
-template <int NDIM>
+// eq. (2): p = (E - rho |u|^2 / 2 - Pi) / Gamma; the quotients as div64<T>.
+template <int NDIM, typename T = double>
 __device__ __forceinline__ void cons_prim(const double* u, double* q) {
   const double rho = u[0];
+  const Div64<T> by_rho(rho);
   double vel[NDIM];
 #pragma unroll
-  for (int a = 0; a < NDIM; a++) vel[a] = u[1 + a] / rho;
+  for (int a = 0; a < NDIM; a++) vel[a] = by_rho(u[1 + a]);
   double ke = vel[0] * vel[0];
 #pragma unroll
   for (int a = 1; a < NDIM; a++) ke = ke + vel[a] * vel[a];
@@ -106,18 +130,18 @@ __device__ __forceinline__ void cons_prim(const double* u, double* q) {
   q[0] = rho;
 #pragma unroll
   for (int a = 0; a < NDIM; a++) q[1 + a] = vel[a];
-  q[1 + NDIM] = (E - 0.5 * rho * ke - P) / G;
+  q[1 + NDIM] = div64<T>(E - 0.5 * rho * ke - P, G);
   q[2 + NDIM] = G;
   q[3 + NDIM] = P;
 }
 
-template <int NDIM>
+template <int NDIM, typename T = double>
 __device__ __forceinline__ void cell_prim(const double* U, int64_t N,
                                           int64_t cell, double* q) {
   double u[4 + NDIM];
 #pragma unroll
   for (int k = 0; k < 4 + NDIM; k++) u[k] = U[k * N + cell];
-  cons_prim<NDIM>(u, q);
+  cons_prim<NDIM, T>(u, q);
 }
 
 template <int NDIM>
@@ -321,7 +345,7 @@ __device__ __forceinline__ void face_flux(const S& st, int weights, int mood,
     a = T(rb) * c / T(2);
     b = qdiv<T>(T(1), c2);
     bd = double(b);
-    gd = 1.0 / double(T(rb) * c);
+    gd = div64<T>(1.0, double(T(rb) * c));
     if (sizeof(T) == 8) {
       bd = 1.0 / double(c2);
     }
@@ -399,7 +423,7 @@ __device__ __forceinline__ void face_params(const S& st, T& a, T& b, double& bd,
   a = T(rb) * c / T(2);
   b = qdiv<T>(T(1), c2);
   bd = double(b);
-  gd = 1.0 / double(T(rb) * c);
+  gd = div64<T>(1.0, double(T(rb) * c));
   if (sizeof(T) == 8) {
     bd = 1.0 / double(c2);
   }

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     const int64_t li = bc_index(l, geo.nL, g.bc_lo, g.bc_hi, flip);
     const int64_t cell = a * geo.sA + li * geo.sL + tt * geo.sT;
     double q[NC];
-    cell_prim<NDIM>(g.Uin, N, cell, q);
+    cell_prim<NDIM, T>(g.Uin, N, cell, q);
     if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
     if (flip) q[1 + D] = -q[1 + D];
 #pragma unroll
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
 
   // 3. cells
-  const double dx = g.dx[D];
+  const Div64<T> bydx(g.dx[D]);
   for (int e = tid; e < TW * TL; e += NTHR) {
     const int w = D == 0 ? e / TL : e % TW;
     const int j = D == 0 ? e % TL : e / TW;
@@ -206,10 +206,10 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
 #pragma unroll
     for (int k = 0; k < NC; k++) {
       const int kc = axis_comp<NDIM, D>(k);
-      double r = -(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])) / dx;
+      double r = bydx(-(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])));
       if (k >= 3 + (NDIM - 1)) {
         const double phi = sq[lidx(kc, w, j + 3)];
-        r = r + phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])) / dx;
+        r = r + bydx(phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])));
       }
       double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
     const int64_t li = bc_index(l, geo.nL, g.bc_lo, g.bc_hi, flip);
     const int64_t cell = a * geo.sA + li * geo.sL + tt * geo.sT;
     double q[NC];
-    cell_prim<NDIM>(g.Uin, N, cell, q);
+    cell_prim<NDIM, T>(g.Uin, N, cell, q);
     if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
     if (flip) q[1 + D] = -q[1 + D];
 #pragma unroll
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
 
   // 3. cells
-  const double dx = g.dx[D];
+  const Div64<T> bydx(g.dx[D]);
   for (int e = tid; e < TW * TL; e += NTHR) {
     const int w = D == 0 ? e / TL : e % TW;
     const int j = D == 0 ? e % TL : e / TW;
@@ -360,10 +360,10 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
 #pragma unroll
     for (int k = 0; k < NC; k++) {
       const int kc = axis_comp<NDIM, D>(k);
-      double r = -(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])) / dx;
+      double r = bydx(-(double(sf[fidx(k, w, j + 1)]) - double(sf[fidx(k, w, j)])));
       if (k >= 3 + (NDIM - 1)) {
         const double phi = sq[lidx(kc, w, j + 3)];
-        r = r + phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])) / dx;
+        r = r + bydx(phi * (double(sf[fidx(NC, w, j + 1)]) - double(sf[fidx(NC, w, j)])));
       }
       double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
