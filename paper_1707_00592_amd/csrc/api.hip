@@ -179,14 +179,31 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
   return hipSuccess;
 }
 
+// Whether a step forms its time step inside its first stage: CFL steps of
+// the fused 2D stage (not the learned weights, which run split sweeps).
+bool fused_dt(const isweno_grid* g, const isweno_opts* o) {
+  return o->cfl > 0.0 && g->ndim == 2 && o->weights != ISWENO_W_MLP;
+}
+
+// Per-tile maxima a step with fused_dt stores: one per tile (else none).
+int64_t dt_slots(const isweno_grid* g, const isweno_opts* o) {
+  return fused_dt(g, o) ? isw::stage2d_tiles(g->n[0], g->n[1]) : 0;
+}
+
 // One RK3 step on stream s: the time step (when cfl > 0), then the three
-// stages, with the intermediate states in U1 and U2 (nc*N each) and the
-// time-step reduction words maxbits (two, zero on entry, left zero).
+// stages, with the intermediate states in U1 and U2 (nc*N each), the
+// time-step words maxbits (two, zero on entry, left zero) and, for
+// fused_dt, the per-tile maxima in part (dt_slots).  With fused_dt the
+// first stage writes L(U) into U1 and its tiles' max wave speeds, one
+// workgroup turns those into dt, and the second stage reads U + dt L: the
+// same states, bit for bit, without a pass of its own over U.
 hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
                        double* dt, isweno_stats* stats, double* U1, double* U2,
-                       unsigned long long* maxbits, bool timed, hipStream_t s) {
+                       unsigned long long* maxbits, unsigned long long* part, bool timed,
+                       hipStream_t s) {
   hipError_t e;
-  if (o->cfl > 0.0) {
+  const bool fused = fused_dt(g, o);
+  if (o->cfl > 0.0 && !fused) {
     KTimer t(timed ? c : nullptr, ISWENO_K_CFL);
     if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, maxbits, dt, c->ncu,
                              s, t.ev)) != hipSuccess)
@@ -195,36 +212,64 @@ hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o
   isw::SweepArgs a = base_args(g, o, stats);
   a.dt = dt;
   a.U0 = U;
-  // stage 1: U1 = U + dt L(U)
-  a.Uin = U;
-  a.Uout = U1;
-  if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, timed, s)) != hipSuccess) return e;
-  // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-  a.Uin = U1;
-  a.Uout = U2;
-  if ((e = stage(c, g, o, a, U2, isw::OUT_RK2, timed, s)) != hipSuccess) return e;
+  if (fused) {
+    // stage 1: L(U) into U1, the tiles' max wave speeds into part; dt
+    a.Uin = U;
+    a.Rout = U1;
+    a.cflp = part;
+    if ((e = stage(c, g, o, a, U1, isw::OUT_RK1L, timed, s)) != hipSuccess) return e;
+    {
+      KTimer t(timed ? c : nullptr, ISWENO_K_CFL);
+      if ((e = isw::launch_cfl_final(part, dt_slots(g, o), o->cfl, o->dt_max, dt, s, t.ev)) !=
+          hipSuccess)
+        return e;
+    }
+    // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1)), U1 = U + dt L(U) formed on the fly
+    a.cflp = nullptr;
+    a.R = U1;
+    a.Uout = U2;
+    if ((e = stage(c, g, o, a, U2, isw::OUT_RK2L, timed, s)) != hipSuccess) return e;
+  } else {
+    // stage 1: U1 = U + dt L(U)
+    a.Uin = U;
+    a.Uout = U1;
+    if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, timed, s)) != hipSuccess) return e;
+    // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+    a.Uin = U1;
+    a.Uout = U2;
+    if ((e = stage(c, g, o, a, U2, isw::OUT_RK2, timed, s)) != hipSuccess) return e;
+  }
   // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)); partial sums in U1
+  a.R = nullptr;
   a.Uin = U2;
   a.Uout = U;
   return stage(c, g, o, a, U1, isw::OUT_RK3, timed, s);
 }
 
-// Workspace of the context: U1 = ws, U2 = ws + nc*N.
+// Workspace of the context: U1 = ws, U2 = ws + nc*N, then the per-tile
+// maxima of a fused_dt step.
+size_t ws_bytes(const isweno_grid* g, const isweno_opts* o) {
+  const size_t sz = (size_t)(4 + g->ndim) * (size_t)ncells(g);
+  return 2 * sz * sizeof(double) + (size_t)dt_slots(g, o) * sizeof(unsigned long long);
+}
+
 hipError_t enqueue_rk3_ws(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
                           double* dt, isweno_stats* stats, hipStream_t s) {
   const size_t sz = (size_t)(4 + g->ndim) * (size_t)ncells(g);
-  return enqueue_rk3(c, g, o, U, dt, stats, c->ws, c->ws + sz, c->maxbits, true, s);
+  auto* part = reinterpret_cast<unsigned long long*>(c->ws + 2 * sz);
+  return enqueue_rk3(c, g, o, U, dt, stats, c->ws, c->ws + sz, c->maxbits, part, true, s);
 }
 
 // ---------------------------------------------------------------------------
 // Scratch of the allocation-free step (isweno_rk3_step_noalloc): the
-// time-step reduction words in its first kCflWordsBytes, then U1 and U2.  A device
+// time-step reduction words in its first kCflWordsBytes, then U1, U2 and
+// the per-tile maxima of a step that forms dt in its first stage.  A device
 // global: every GPU the library runs on holds its own copy from the load of
 // the library's code object until the process ends.  Host code never uses
 // the array's name as an address: scratch_addr() returns this device's copy,
 // looked up once per device with hipGetSymbolAddress.
 // ---------------------------------------------------------------------------
-constexpr size_t kScratchStates = (size_t)128 << 20;  // bytes for U1 and U2
+constexpr size_t kScratchStates = (size_t)128 << 20;  // bytes for U1, U2 (and the maxima)
 static __device__ __align__(256) unsigned char scratch[isw::kCflWordsBytes + kScratchStates];
 
 constexpr int kMaxDevices = 64;
@@ -349,10 +394,7 @@ int isweno_rk3_step(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, d
   if ((r = check_grid(g)) != ISWENO_OK) return r;
   if ((r = check_opts(o)) != ISWENO_OK) return r;
   if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
-  const int64_t N = ncells(g);
-  const int nc = 4 + g->ndim;
-  const size_t sz = (size_t)nc * (size_t)N;
-  if ((r = ensure_ws(c, 2 * sz * sizeof(double))) != ISWENO_OK) return r;
+  if ((r = ensure_ws(c, ws_bytes(g, o))) != ISWENO_OK) return r;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // Launch directly with kernel timing on (events bracket each kernel) and
   // when dt is clipped (dt_max > 0: a value that usually changes from call
@@ -411,7 +453,9 @@ int isweno_rk3_step_noalloc(isweno_ctx* c, const isweno_grid* g, const isweno_op
   if ((r = check_opts(o)) != ISWENO_OK) return r;
   const int64_t N = ncells(g);
   const int nc = 4 + g->ndim;
-  if ((uint64_t)N > kScratchStates / (2 * sizeof(double) * (size_t)nc)) return ISWENO_ERR_ARG;
+  if ((uint64_t)N > kScratchStates / (2 * sizeof(double) * (size_t)nc) ||
+      ws_bytes(g, o) > kScratchStates)
+    return ISWENO_ERR_ARG;
   if (hipSetDevice(c->device) != hipSuccess) return ISWENO_ERR_DEVICE;
   unsigned char* base = scratch_addr(c->device);  // resolved by isweno_create
   if (!base) return ISWENO_ERR_DEVICE;
@@ -419,10 +463,11 @@ int isweno_rk3_step_noalloc(isweno_ctx* c, const isweno_grid* g, const isweno_op
   auto* maxbits = reinterpret_cast<unsigned long long*>(base);
   double* U1 = reinterpret_cast<double*>(base + isw::kCflWordsBytes);
   double* U2 = U1 + (size_t)nc * (size_t)N;
+  auto* part = reinterpret_cast<unsigned long long*>(U2 + (size_t)nc * (size_t)N);
   // the reduction words keep whatever the previous call on this GPU left:
   // clear them with a kernel (no memset node, should a caller capture this)
   if (o->cfl > 0.0 && isw::launch_zero_cfl(maxbits, s) != hipSuccess) return ISWENO_ERR_DEVICE;
-  return enqueue_rk3(c, g, o, U, dt, stats, U1, U2, maxbits, false, s) == hipSuccess
+  return enqueue_rk3(c, g, o, U, dt, stats, U1, U2, maxbits, part, false, s) == hipSuccess
              ? ISWENO_OK
              : ISWENO_ERR_DEVICE;
 }

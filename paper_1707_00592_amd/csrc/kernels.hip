@@ -9,15 +9,35 @@
 namespace isw {
 
 // ---------------------------------------------------------------------------
-// Time step in one launch: per-cell sum_d (|u_d| + c)/dx_d, the workgroup's
-// max, a device-wide max through an integer atomic on the bits of the
-// (positive) doubles, which order as the doubles do (a NaN above every
-// number), and dt formed by the workgroup that finishes last, found by a
-// ticket counter.  words[kCflMax] and words[kCflTicket] start zero and are
-// left zero.
+// Time step in one launch: per-cell sum_d (|u_d| + c)/dx_d (cell_speed), the
+// workgroup's max, then cfl_ticket: a device-wide max through an integer
+// atomic on the doubles' bits and dt formed by the workgroup that finishes
+// last.  The words start zero and are left zero.
 // ---------------------------------------------------------------------------
 constexpr int kCflThreads = 1024;
 constexpr int kCflCells = 2;  // cells per lane and pass, loaded before any arithmetic
+constexpr int kCflMax = 0, kCflTicket = 1;  // the time-step words
+
+// One workgroup's end of the reduction (one lane): its max (bits) into the
+// max word by an integer atomic, then a ticket; the workgroup holding the
+// last of nblocks tickets forms dt = cfl / max (clipped to dt_max > 0),
+// writes it and clears both words.
+__device__ __forceinline__ void cfl_ticket(unsigned long long* w, unsigned long long bits,
+                                           unsigned nblocks, double cfl, double dt_max,
+                                           double* dt) {
+  atomicMax(&w[kCflMax], bits);
+  __threadfence();
+  if (atomicAdd(&w[kCflTicket], 1ull) == nblocks - 1) {
+    // every other workgroup's max precedes its ticket
+    __threadfence();
+    const double mx = __longlong_as_double((long long)atomicMax(&w[kCflMax], 0ull));
+    double h = cfl / mx;
+    if (dt_max > 0.0 && h > dt_max) h = dt_max;
+    *dt = h;
+    atomicExch(&w[kCflMax], 0ull);
+    atomicExch(&w[kCflTicket], 0ull);
+  }
+}
 
 template <int NDIM>
 __global__ __launch_bounds__(kCflThreads) void cfl_kernel(
@@ -41,37 +61,48 @@ __global__ __launch_bounds__(kCflThreads) void cfl_kernel(
       if (c0 + (int64_t)r * kCflThreads >= N) continue;
       double q[NC];
       cons_prim<NDIM>(u[r], q);
-      const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
-      double sp = (fabs(q[1]) + cs) / dxs[0];
-#pragma unroll
-      for (int a = 1; a < NDIM; a++) sp = sp + (fabs(q[1 + a]) + cs) / dxs[a];
+      const double sp = cell_speed<NDIM>(q, dxs);
       m = (sp > m || sp != sp) ? sp : m;
     }
   }
-  unsigned long long b = (unsigned long long)__double_as_longlong(m);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long x = __shfl_xor(b, o);
-    b = x > b ? x : b;
-  }
   __shared__ unsigned long long red[kCflThreads / 64];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  wave_max_bits(m, red);
   __syncthreads();
   if (threadIdx.x == 0) {
+    unsigned long long b = red[0];
     for (int w = 1; w < kCflThreads / 64; w++) b = red[w] > b ? red[w] : b;
-    atomicMax(&words[kCflMax], b);
-    __threadfence();
-    if (atomicAdd(&words[kCflTicket], 1ull) == gridDim.x - 1) {
-      // every other workgroup's max precedes its ticket
-      __threadfence();
-      const double mx = __longlong_as_double((long long)atomicMax(&words[kCflMax], 0ull));
-      double h = cfl / mx;
-      if (dt_max > 0.0 && h > dt_max) h = dt_max;
-      *dt = h;
-      atomicExch(&words[kCflMax], 0ull);
-      atomicExch(&words[kCflTicket], 0ull);
-    }
+    cfl_ticket(words, b, gridDim.x, cfl, dt_max, dt);
   }
+}
+
+// dt from the per-workgroup maxima the first fused 2D stage stored (one
+// workgroup): the max over them, dt = cfl / max, clipped to dt_max > 0.
+__global__ __launch_bounds__(kCflThreads) void cfl_final_kernel(const unsigned long long* part,
+                                                                 int64_t n, double cfl,
+                                                                 double dt_max, double* dt) {
+  unsigned long long b = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kCflThreads) b = part[i] > b ? part[i] : b;
+  __shared__ unsigned long long red[kCflThreads / 64];
+  wave_max_bits(__longlong_as_double((long long)b), red);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    b = red[0];
+    for (int w = 1; w < kCflThreads / 64; w++) b = red[w] > b ? red[w] : b;
+    double h = cfl / __longlong_as_double((long long)b);
+    if (dt_max > 0.0 && h > dt_max) h = dt_max;
+    *dt = h;
+  }
+}
+
+hipError_t launch_cfl_final(const unsigned long long* part, int64_t n, double cfl,
+                            double dt_max, double* dt, hipStream_t s, LaunchEvents ev) {
+  if (n < 1) return hipErrorInvalidValue;
+  if (ev.start)
+    hipExtLaunchKernelGGL(cfl_final_kernel, dim3(1), dim3(kCflThreads), 0, s, ev.start, ev.stop, 0,
+                          part, n, cfl, dt_max, dt);
+  else
+    hipLaunchKernelGGL(cfl_final_kernel, dim3(1), dim3(kCflThreads), 0, s, part, n, cfl, dt_max, dt);
+  return hipGetLastError();
 }
 
 hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int mode,

@@ -25,13 +25,13 @@ hipError_t launch_sweep_cut(int precision, int ndim, int D, const SweepArgs& a, 
                             bool readR, hipStream_t s, LaunchEvents ev = {});
 
 // One whole RK stage of a 2D grid (x and y faces of each tile in one
-// launch); mode is OUT_RHS or one of the OUT_RK* modes.  Not for the
-// learned weights.
+// launch); mode is OUT_RHS or one of the OUT_RK* modes (OUT_RK1L and
+// OUT_RK2L: the step's time step formed inside the first stage).  Not for
+// the learned weights.
 hipError_t launch_stage2d(int precision, const SweepArgs& a, int mode, hipStream_t s,
                           LaunchEvents ev = {});
 
-// Device words of the time-step reduction (64-bit): the max, the ticket.
-constexpr int kCflMax = 0, kCflTicket = 1;
+// Bytes of the time-step words (the max and the ticket).
 constexpr size_t kCflWordsBytes = 256;
 
 // dt = cfl / max sum_d (|u_d| + c)/dx_d (clipped to dt_max > 0), one launch;
@@ -39,6 +39,15 @@ constexpr size_t kCflWordsBytes = 256;
 hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double* dx,
                       double cfl, double dt_max, unsigned long long* words, double* dt,
                       int ncu, hipStream_t s, LaunchEvents ev = {});
+
+// dt = cfl / max over n per-workgroup maxima (bits of positive doubles, as
+// the first fused 2D stage stores them), clipped to dt_max > 0; one
+// workgroup.
+hipError_t launch_cfl_final(const unsigned long long* part, int64_t n, double cfl,
+                            double dt_max, double* dt, hipStream_t s, LaunchEvents ev = {});
+
+// The number of workgroups (tiles) of the fused 2D stage on an nx x ny grid.
+int64_t stage2d_tiles(int64_t nx, int64_t ny);
 
 // Zeroes the time-step words by a kernel (used instead of a
 // memset, which a captured graph should not contain).

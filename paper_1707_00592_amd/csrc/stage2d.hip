@@ -64,6 +64,10 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   __shared__ int s_queue[GATHER ? NTHR : 1];
   __shared__ int s_nq[GATHER ? 2 : 1];
   __shared__ T sfx[GATHER ? (NC + 1) * NFX : 1];
+  // OUT_RK1L: this stage also finds its tile's max wave speed (the step's
+  // time step); OUT_RK2L: its input is U0 + dt R
+  constexpr bool SPEEDS = MODE == OUT_RK1L, FROM_L = MODE == OUT_RK2L;
+  __shared__ unsigned long long s_red[SPEEDS ? NTHR / 64 : 1];
 
   const int64_t nx = g.n[0], ny = g.n[1], N = nx * ny;
   // Tile order.  The hardware deals workgroups to its 8 XCDs in turn
@@ -97,11 +101,17 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
   }
   __syncthreads();
-  if (s_skip) return;
+  if (s_skip) {
+    if (SPEEDS && tid == 0) g.cflp[blockIdx.x] = 0ull;
+    return;
+  }
 
   // 1. stage primitives: the tile's interior cells, its rows extended by 3
   // cells each way along x and its columns by 3 each way along y
   bool bad = false;
+  double m = 0.0, h1 = 0.0;  // SPEEDS: the lane's max wave speed; FROM_L: dt
+  if constexpr (FROM_L) h1 = *g.dt;
+  const double dxs[2] = {g.dx[0], g.dx[1]};
   for (int e = tid; e < QROW; e += NTHR) {
     const int yy = e / SX, xx = e % SX;
     const int64_t gxl = gx0 + xx - 3, gyl = gy0 + yy - 3;
@@ -115,9 +125,20 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     if (xhalo) ix = bc_index(gxl, nx, g.bcl[0], g.bch[0], flip);
     if (yhalo) iy = bc_index(gyl, ny, g.bcl[1], g.bch[1], flip);
     const int64_t cell = iy * nx + ix;
-    double q[NC];
-    cell_prim<NDIM, T>(g.Uin, N, cell, q);
-    if (colin && rowin) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
+    double u[NC], q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      if constexpr (FROM_L) u[c] = g.U0[c * N + cell] + h1 * g.R[c * N + cell];
+      else u[c] = g.Uin[c * N + cell];
+    }
+    cons_prim<NDIM, T>(u, q);
+    if (colin && rowin) {
+      bad = bad || !cell_ok_u<NDIM>(u, q);
+      if constexpr (SPEEDS) {
+        const double sp = cell_speed<NDIM, T>(q, dxs);
+        m = (sp > m || sp != sp) ? sp : m;
+      }
+    }
     if (flip) {
       if (xhalo) q[1] = -q[1];
       else q[2] = -q[2];
@@ -125,9 +146,17 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
 #pragma unroll
     for (int c = 0; c < NC; c++) sq[c * QROW + e] = q[c];
   }
+  if constexpr (SPEEDS) wave_max_bits(m, s_red);
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
+  if constexpr (SPEEDS) {
+    if (tid == 0) {
+      unsigned long long b = s_red[0];
+      for (int w = 1; w < NTHR / 64; w++) b = s_red[w] > b ? s_red[w] : b;
+      g.cflp[blockIdx.x] = b;
+    }
+  }
 
   int my3[2] = {0, 0}, my1[2] = {0, 0}, mys[2] = {0, 0};
   const int wts = kernel_weights<CUT>(g.weights);
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
       }
       const double L = rx[kc] + r;
       const int64_t o = kc * N + cell;
-      if (MODE == OUT_RHS) {
+      if (MODE == OUT_RHS || MODE == OUT_RK1L) {
         g.Rout[o] = L;
       } else {
         const double h = *g.dt;
@@ -321,6 +350,10 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
           g.Uout[o] = g.U0[o] + h * L;
         } else if (MODE == OUT_RK2) {
           g.Uout[o] = 0.75 * g.U0[o] + 0.25 * (g.Uin[o] + h * L);
+        } else if (MODE == OUT_RK2L) {
+          // the stage input U0 + dt R, formed as stage 1 would have written it
+          const double u0 = g.U0[o];
+          g.Uout[o] = 0.75 * u0 + 0.25 * ((u0 + h * g.R[o]) + h * L);
         } else {
           g.Uout[o] = (1.0 / 3.0) * g.U0[o] + (2.0 / 3.0) * (g.Uin[o] + h * L);
         }
@@ -329,12 +362,18 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   }
 }
 
+int64_t stage2d_tiles(int64_t nx, int64_t ny) {
+  return ((nx + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+}
+
 template <typename T, int MODE, bool CUT, bool GATHER>
 static hipError_t launch_t(const SweepArgs& a, hipStream_t s, LaunchEvents ev) {
   // one workgroup per tile: the kernel maps block b to tile (b & 7, b >> 3)
-  // of the XCD-ordered list of exactly this many tiles
+  // of the XCD-ordered list of exactly this many tiles (OUT_RK1L: and
+  // stores one max per tile into cflp)
   if (a.n[0] < 1 || a.n[1] < 1 || a.n[2] != 1) return hipErrorInvalidValue;
-  const int64_t blocks = ((a.n[0] + kTX - 1) / kTX) * ((a.n[1] + kTY - 1) / kTY);
+  if ((MODE == OUT_RK1L && !a.cflp) || (MODE == OUT_RK2L && !a.R)) return hipErrorInvalidValue;
+  const int64_t blocks = stage2d_tiles(a.n[0], a.n[1]);
   if (blocks <= 0) return hipSuccess;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(kThreads);
@@ -353,6 +392,8 @@ static hipError_t launch_g(const SweepArgs& a, int mode, hipStream_t s, LaunchEv
     case OUT_RK1: return launch_t<T, OUT_RK1, CUT, GATHER>(a, s, ev);
     case OUT_RK2: return launch_t<T, OUT_RK2, CUT, GATHER>(a, s, ev);
     case OUT_RK3: return launch_t<T, OUT_RK3, CUT, GATHER>(a, s, ev);
+    case OUT_RK1L: return launch_t<T, OUT_RK1L, CUT, GATHER>(a, s, ev);
+    case OUT_RK2L: return launch_t<T, OUT_RK2L, CUT, GATHER>(a, s, ev);
     default: return hipErrorInvalidValue;
   }
 }

@@ -28,7 +28,10 @@ enum OutMode {
   OUT_RHS = 1,      // dUdt = (R +) r_D
   OUT_RK1 = 2,      // Uout = U0 + dt L
   OUT_RK2 = 3,      // Uout = 3/4 U0 + 1/4 (Uin + dt L)
-  OUT_RK3 = 4       // Uout = 1/3 U0 + 2/3 (Uin + dt L)
+  OUT_RK3 = 4,      // Uout = 1/3 U0 + 2/3 (Uin + dt L)
+  // the time step inside the first two stages (fused 2D stage only):
+  OUT_RK1L = 5,     // Rout = L(Uin), and each workgroup's max wave speed of Uin
+  OUT_RK2L = 6      // as OUT_RK2 with the stage input U0 + dt R, R = L(U0) of OUT_RK1L
 };
 
 enum { ST_OK = 0, ST_NONPHYSICAL = -4 };
@@ -56,6 +59,8 @@ struct SweepArgs {
   const uint16_t* mlp; // packed bf16 network (learned weights only)
   float mlp_thr;
   unsigned long long* shortcut;  // 256 x 3 counters of shortcut field-sides, or null
+  // OUT_RK1L: one max wave speed per workgroup (the bits of the double)
+  unsigned long long* cflp;
 };
 
 // Sum of an int over the 64 lanes of a wave (every lane active).
@@ -144,12 +149,46 @@ __device__ __forceinline__ void cell_prim(const double* U, int64_t N,
   cons_prim<NDIM, T>(u, q);
 }
 
+// Time step (the CFL condition of Secs. 5 and 6): one cell's
+// sum_d (|u_d| + c)/dx_d from its axis-order primitives q, the quotients as
+// div64<T>.
+template <int NDIM, typename T = double>
+__device__ __forceinline__ double cell_speed(const double* q, const double* dx) {
+  const double cs = sqrt(sound2<double>(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]));
+  double sp = div64<T>(fabs(q[1]) + cs, dx[0]);
+#pragma unroll
+  for (int a = 1; a < NDIM; a++) sp = sp + div64<T>(fabs(q[1 + a]) + cs, dx[a]);
+  return sp;
+}
+
+// Each wave's max of m over its lanes, as the bits of the double (positive
+// doubles order as their bits do; a NaN orders above every number), into
+// red[wave]; the caller combines red after a barrier.
+__device__ __forceinline__ void wave_max_bits(double m, unsigned long long* red) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(m);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(b, o);
+    b = x > b ? x : b;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+}
+
 template <int NDIM>
 __device__ __forceinline__ bool cell_ok(const double* U, int64_t N,
                                         int64_t cell, const double* q) {
   bool fin = true;
 #pragma unroll
   for (int k = 0; k < 4 + NDIM; k++) fin = fin && isfinite(U[k * N + cell]);
+  return fin && admissible(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]);
+}
+
+// The same check on a cell's conservative values u (already loaded).
+template <int NDIM>
+__device__ __forceinline__ bool cell_ok_u(const double* u, const double* q) {
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 4 + NDIM; k++) fin = fin && isfinite(u[k]);
   return fin && admissible(q[0], q[1 + NDIM], q[2 + NDIM], q[3 + NDIM]);
 }
 

@@ -167,6 +167,48 @@ def test_cfl_dt_matches_oracle(lib, ctx):
         assert float(dt.item()) == ref
 
 
+def test_time_step_inside_the_first_stage(lib, ctx):
+    """A CFL step of a 2D grid forms its time step inside the first stage
+    (each tile's max wave speed of U^n, then one workgroup); dt must equal the
+    standalone reduction's and the oracle's bit for bit, and the step's state
+    the oracle's.  Grids with tile counts that are not multiples of 8, tiles
+    that hold only a few cells, reflective and periodic ends, both weight
+    forms and both MOOD forms; the float form's dt within 4 ulp."""
+    torch = _torch()
+    cases = [((150, 70), 1, "transmissive"), ((16, 16), 2, "reflective"),
+             ((31, 33), 3, "periodic"), ((1, 40), 4, "periodic"), ((47, 1), 5, "transmissive")]
+    for shape, seed, bc in cases:
+        p = wl.random_two_phase(shape, seed=seed)
+        b = {"transmissive": 0, "periodic": 1, "reflective": 2}[bc]
+        og = oracle.make_grid(p.n, p.dx, [b, b], [b, b])
+        ig = lib.make_grid(p.n, p.dx, [b, b], [b, b])
+        for weights in (lib.W_MODIFIED, lib.W_CUTOFF):
+            for mood in (True, lib.MOOD_GATHER):
+                oo = oracle.make_opts(weights=weights, mood=True, cfl=0.5)
+                ref_dt = oracle.cfl_dt(p.U, og, oo)
+                ref_U = oracle.rk3_step(p.U, og, ref_dt, oo)[0]
+                o = lib.make_opts(weights=weights, mood=mood, cfl=0.5)
+                dt_alone = torch.zeros(1, dtype=torch.float64, device="cuda")
+                ctx.cfl_dt(_dev(p.U), ig, o, dt_alone)
+                U = _dev(p.U)
+                dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+                ctx.rk3_step(U, ig, o, dt)
+                torch.cuda.synchronize()
+                got_dt = float(dt.item())
+                same = np.array_equal(U.cpu().numpy().view(np.uint64), ref_U.view(np.uint64))
+                print(f"[fused dt] {shape} {bc} w{weights} mood {int(mood)}: dt {got_dt!r} "
+                      f"oracle {ref_dt!r} state bitwise {same}", flush=True)
+                assert got_dt == ref_dt == float(dt_alone.item())
+                assert same
+        # the float form: its primitive recovery divides through reciprocals
+        o32 = lib.make_opts(precision=lib.FP32, cfl=0.5)
+        U = _dev(p.U)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.rk3_step(U, ig, o32, dt)
+        ref_dt = oracle.cfl_dt(p.U, og, oracle.make_opts(cfl=0.5))
+        assert abs(float(dt.item()) - ref_dt) <= 4 * np.spacing(ref_dt)
+
+
 def test_gas_liquid_shock_tube_run_matches_oracle(lib, ctx):
     """The 200-cell water/air shock tube run to t = 2.4e-4 s with the CFL
     time step (about 255 RK3 steps), MOOD off as in Sec. 5."""
