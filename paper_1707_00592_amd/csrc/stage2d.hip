@@ -32,10 +32,11 @@ constexpr int kTX = 15, kTY = 16, kThreads = 256;
 constexpr int kSX = kTX + 6, kSY = kTY + 6;  // staged rectangle; its corners stay unused
 constexpr int kQROW = kSX * kSY;
 
+template <typename E>
 struct LdsStencil2 {
-  const double* base;  // LDS row of component 0, stencil position 0
+  const E* base;  // LDS row of component 0, stencil position 0
   int pstride;
-  __device__ __forceinline__ double operator()(int c, int j) const {
+  __device__ __forceinline__ E operator()(int c, int j) const {
     return base[c * kQROW + j * pstride];
   }
 };
@@ -52,7 +53,9 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   constexpr int NFX = (TX + 1) * TY;  // 256 x faces: lane = 16 row + face
   constexpr int NFY = TX * (TY + 1);  // 255 y faces: face (x, fy) at fy * TX + x
   static_assert(NFX == NTHR && NFY <= NTHR, "one face per lane in each phase");
-  __shared__ double sq[NC * QROW];  // primitives [c][yy][xx]
+  // primitives [c][yy][xx], recovered in FP64 and staged in the arithmetic's
+  // type (the float form reconstructs from float values anyway)
+  __shared__ T sq[NC * QROW];
   // y-face fluxes and v* in the arithmetic's type (the float form's fluxes
   // are float values, so float storage is exact)
   __shared__ T sfy[(NC + 1) * NFY];
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
       else q[2] = -q[2];
     }
 #pragma unroll
-    for (int c = 0; c < NC; c++) sq[c * QROW + e] = q[c];
+    for (int c = 0; c < NC; c++) sq[c * QROW + e] = T(q[c]);
   }
   if constexpr (SPEEDS) wave_max_bits(m, s_red);
   if (bad) s_status = ST_NONPHYSICAL;
@@ -162,13 +165,13 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   const int wts = kernel_weights<CUT>(g.weights);
   const Div64<T> bydx(g.dx[0]), bydy(g.dx[1]);
   auto xstencil = [&](int f) {  // x face (f % 16, f / 16)
-    LdsStencil2 st;
+    LdsStencil2<T> st;
     st.base = &sq[(f / 16 + 3) * SX + f % 16];
     st.pstride = 1;
     return st;
   };
   auto ystencil = [&](int f) {  // y face (f % TX, f / TX)
-    LdsStencil2 st;
+    LdsStencil2<T> st;
     st.base = &sq[(f / TX) * SX + f % TX + 3];
     st.pstride = SX;
     return st;
