@@ -40,10 +40,11 @@ struct BatchArgs {
   double eps;
 };
 
+template <typename E>
 struct Lds1 {
-  const double* base;
+  const E* base;
   int cstride;
-  __device__ __forceinline__ double operator()(int c, int j) const {
+  __device__ __forceinline__ E operator()(int c, int j) const {
     return base[c * cstride + j];
   }
 };
@@ -51,8 +52,10 @@ struct Lds1 {
 template <typename T, int TL, int MODE, bool CUT>
 __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
   constexpr int NC = 5, NP = TL + 6, NF = TL + 1, NTHR = TL + 1;
-  __shared__ double sq[NC * NP];
-  __shared__ double sf[(NC + 1) * NF];
+  // FP64 primitives and the face values, both in the arithmetic's type (the
+  // float form reconstructs from float values and its fluxes are float)
+  __shared__ T sq[NC * NP];
+  __shared__ T sf[(NC + 1) * NF];
   __shared__ int s_status;
   const int tid = threadIdx.x;
   if (tid == 0) s_status = ST_OK;
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       if (p >= 3 && p < 3 + len) bad = bad || !cell_ok<1>(g.Uin, total, lo + li, q);
       if (flip) q[1] = -q[1];
 #pragma unroll
-      for (int c = 0; c < NC; c++) sq[c * NP + p] = q[c];
+      for (int c = 0; c < NC; c++) sq[c * NP + p] = T(q[c]);
     }
     if (bad) {
       s_status = ST_NONPHYSICAL;
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
     }
     __syncthreads();
     for (int j = tid; j <= len; j += NTHR) {
-      Lds1 st;
+      Lds1<T> st;
       st.base = &sq[j];
       st.cstride = NP;
       double F[NC], us;
@@ -99,8 +102,8 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
         my1 += n1;
       }
 #pragma unroll
-      for (int k = 0; k < NC; k++) sf[k * NF + j] = F[k];
-      sf[NC * NF + j] = us;
+      for (int k = 0; k < NC; k++) sf[k * NF + j] = T(F[k]);
+      sf[NC * NF + j] = T(us);
     }
     __syncthreads();
     const Div64<T> bydx(g.dx[prob]);
@@ -109,8 +112,10 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       const int64_t cell = lo + l0 + j;
 #pragma unroll
       for (int k = 0; k < NC; k++) {
-        double r = bydx(-(sf[k * NF + j + 1] - sf[k * NF + j]));
-        if (k >= 3) r = r + bydx(sq[k * NP + j + 3] * (sf[NC * NF + j + 1] - sf[NC * NF + j]));
+        double r = bydx(-(double(sf[k * NF + j + 1]) - double(sf[k * NF + j])));
+        if (k >= 3)
+          r = r + bydx(double(sq[k * NP + j + 3]) *
+                       (double(sf[NC * NF + j + 1]) - double(sf[NC * NF + j])));
         const int64_t o = k * total + cell;
         if (MODE == OUT_RK1) {
           g.Uout[o] = g.U0[o] + h * r;

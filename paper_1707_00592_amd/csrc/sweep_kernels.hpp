@@ -14,10 +14,11 @@
 namespace isw {
 
 // LDS accessor for a stencil: component c at stencil position j (0..5).
+template <typename E>
 struct LdsStencil {
-  const double* base;  // component 0, position 0
+  const E* base;  // component 0, position 0
   int cstride, pstride;
-  __device__ __forceinline__ double operator()(int c, int j) const {
+  __device__ __forceinline__ E operator()(int c, int j) const {
     return base[c * cstride + j * pstride];
   }
 };
@@ -25,11 +26,11 @@ struct LdsStencil {
 // The same with the two material rows (Gamma, Pi) stored before the others:
 // base points at component 0, which is row 2; Gamma and Pi sit NC rows
 // before their component number.
-template <int NC>
+template <int NC, typename E>
 struct LdsStencilMatFirst {
-  const double* base;  // component 0 (row 2), position 0
+  const E* base;  // component 0 (row 2), position 0
   int cstride, pstride;
-  __device__ __forceinline__ double operator()(int c, int j) const {
+  __device__ __forceinline__ E operator()(int c, int j) const {
     const int r = c >= NC - 2 ? c - NC : c;
     return base[r * cstride + j * pstride];
   }
@@ -65,10 +66,12 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
   static_assert(TW * NF == NTHR, "one face per thread");
-  // One LDS buffer, two phases.  Faces read the staged primitives sq; the
-  // cells read the face values sf (fluxes and u*, in the arithmetic's type:
-  // the float form's fluxes are float values, so float storage is exact)
-  // and only the Gamma and Pi rows of sq.  In 3D (ALIAS) the rows are stored
+  // One LDS buffer, two phases.  Faces read the staged primitives sq
+  // (recovered in FP64, staged in the arithmetic's type: the float form
+  // reconstructs from float values anyway); the cells read the face values
+  // sf (fluxes and u*, in the arithmetic's type: the float form's fluxes are
+  // float values, so float storage is exact) and only the Gamma and Pi rows
+  // of sq.  In 3D (ALIAS) the rows are stored
   // in the order (Gamma, Pi, rho, u..., p), sf starts after the first two
   // and overwrites the others once every face is evaluated (33 -> 21 KB per
   // FP64 workgroup, 4 -> 5 waves per SIMD); in 1D and 2D registers bound the
@@ -76,12 +79,12 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   // Layouts: D = 0 -> [row][w][p]; D > 0 -> [row][p][w].
   constexpr bool ALIAS = NDIM == 3;
   constexpr int QROW = TW * NP;
-  constexpr int SQ_BYTES = NC * QROW * 8;
-  constexpr int SF_OFF = ALIAS ? 2 * QROW * 8 : SQ_BYTES;
+  constexpr int SQ_BYTES = NC * QROW * (int)sizeof(T);
+  constexpr int SF_OFF = ALIAS ? 2 * QROW * (int)sizeof(T) : SQ_BYTES;
   constexpr int SF_BYTES = (NC + 1) * TW * NF * (int)sizeof(T);
   constexpr int LDS_BYTES = SQ_BYTES > SF_OFF + SF_BYTES ? SQ_BYTES : SF_OFF + SF_BYTES;
   __shared__ __attribute__((aligned(16))) unsigned char lds[LDS_BYTES];
-  double* const sq = reinterpret_cast<double*>(lds);
+  T* const sq = reinterpret_cast<T*>(lds);
   T* const sf = reinterpret_cast<T*>(lds + SF_OFF);
   __shared__ int s_status;
   __shared__ int s_skip;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
     if (flip) q[1 + D] = -q[1 + D];
 #pragma unroll
-    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = q[c];
+    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = T(q[c]);
   }
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   double F[NC], us;
   if (fvalid) {
     const int64_t gl = l0 + fj;  // face index along D (between gl-1 and gl)
-    std::conditional_t<ALIAS, LdsStencilMatFirst<NC>, LdsStencil> st;
+    std::conditional_t<ALIAS, LdsStencilMatFirst<NC, T>, LdsStencil<T>> st;
     st.base = &sq[lidx(0, fw, fj)];
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
   // LDS layouts: D = 0 -> [c][w][p]; D > 0 -> [c][p][w]
-  __shared__ double sq[NC * TW * NP];
+  __shared__ T sq[NC * TW * NP];  // FP64 primitives staged as T
   // face fluxes in the arithmetic's type: the float form's fluxes are
   // float values, so float storage is exact and frees LDS for occupancy
   __shared__ T sf[(NC + 1) * TW * NF];
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
     if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
     if (flip) q[1 + D] = -q[1 + D];
 #pragma unroll
-    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = q[c];
+    for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = T(q[c]);
   }
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(NTHR) void sweep_mlp_kernel(SweepArgs g) {
       w = 0;
       j = 0;
     }
-    LdsStencil st;
+    LdsStencil<T> st;
     st.base = &sq[lidx(0, w, j)];
     st.cstride = D == 0 ? TW * NP : NP * TW;
     st.pstride = D == 0 ? 1 : TW;
