@@ -17,7 +17,10 @@
 //      sum, L = r_x + r_y) and writes dU/dt or the Runge-Kutta stage.
 // Compared with one sweep per axis, neither axis' terms travel through
 // memory and the state is read once per stage; no face evaluation runs with
-// another face's results held in registers.
+// another face's results held in registers.  A CFL step forms its time step
+// in its first stage (OUT_RK1L: L(U^n) and each tile's max wave speed,
+// reduced by one workgroup between the stages) and stages U^n + dt L in the
+// second (OUT_RK2L), so that U^n is not read by a reduction of its own.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
