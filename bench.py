@@ -14,8 +14,8 @@ inputs resident in HBM before the timed region.  `value` is the plain FP64
 path; the FP32 reconstruction/flux form is timed the same way and reported
 with its L1 difference from the FP64 path after the same steps.
 
-Printed: ONE JSON line (rank 0).  --gpus > 1 is refused: this build runs on
-a single GPU.
+Printed: ONE JSON line (rank 0).  --gpus > 1 is refused: the path runs on
+a single GPU (how it would shard is described with the design).
 """
 from __future__ import annotations
 
@@ -618,7 +618,7 @@ def rel_l1(a, b):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
