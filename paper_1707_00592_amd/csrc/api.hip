@@ -147,12 +147,24 @@ isw::SweepArgs base_args(const isweno_grid* g, const isweno_opts* o, isweno_stat
   return a;
 }
 
+// The time step formed inside a 3D stage: the x sweep stores one max wave
+// speed per tile into part, and one workgroup turns the n maxima into dt
+// before the y sweep.
+struct DtInStage {
+  unsigned long long* part;
+  int64_t n;
+  double cfl, dt_max;
+  double* dt;
+};
+
 // One evaluation of L on Uin followed by the output step `mode`; the partial
 // sums of the first ndim-1 axes go to `partial` (which may alias the final
 // output buffer, cell by cell).  timed = false: no timing events or
 // shortcut counts even while timing is enabled (the allocation-free step).
+// fin (3D only): form the step's dt after the x sweep.
 hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw::SweepArgs a,
-                 double* partial, int mode, bool timed, hipStream_t s) {
+                 double* partial, int mode, bool timed, hipStream_t s,
+                 const DtInStage* fin = nullptr) {
   const int nd = g->ndim;
   isweno_ctx* tc = timed ? c : nullptr;
   unsigned long long* shortcut = timed && c->timing ? c->shortcut : nullptr;
@@ -171,38 +183,57 @@ hipError_t stage(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, isw:
     b.R = partial;
     if (!last) b.Rout = partial;
     b.shortcut = shortcut;  // never inside a captured graph
-    KTimer t(tc, ISWENO_K_SWEEP_X + D);
-    const hipError_t e = isw::launch_sweep(o->precision, nd, D, b,
-                                           last ? mode : isw::OUT_PARTIAL, D > 0, s, t.ev);
-    if (e != hipSuccess) return e;
+    int m = last ? mode : isw::OUT_PARTIAL;
+    const bool speeds = fin && D == 0 && nd == 3;
+    if (speeds) {
+      b.cflp = fin->part;
+      m = isw::OUT_PARTIAL_S;
+    }
+    {
+      KTimer t(tc, ISWENO_K_SWEEP_X + D);
+      const hipError_t e = isw::launch_sweep(o->precision, nd, D, b, m, D > 0, s, t.ev);
+      if (e != hipSuccess) return e;
+    }
+    if (speeds) {
+      KTimer t(tc, ISWENO_K_CFL);
+      const hipError_t e =
+          isw::launch_cfl_final(fin->part, fin->n, fin->cfl, fin->dt_max, fin->dt, s, t.ev);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
 
 // Whether a step forms its time step inside its first stage: CFL steps of
-// the fused 2D stage (not the learned weights, which run split sweeps).
+// 2D and 3D grids (not 1D, whose only sweep needs dt, nor the learned
+// weights).
 bool fused_dt(const isweno_grid* g, const isweno_opts* o) {
-  return o->cfl > 0.0 && g->ndim == 2 && o->weights != ISWENO_W_MLP;
+  return o->cfl > 0.0 && g->ndim >= 2 && o->weights != ISWENO_W_MLP;
 }
 
-// Per-tile maxima a step with fused_dt stores: one per tile (else none).
+// Per-tile maxima a step with fused_dt stores: one per tile of the fused 2D
+// stage or of the 3D x sweep (else none).
 int64_t dt_slots(const isweno_grid* g, const isweno_opts* o) {
-  return fused_dt(g, o) ? isw::stage2d_tiles(g->n[0], g->n[1]) : 0;
+  if (!fused_dt(g, o)) return 0;
+  return g->ndim == 2 ? isw::stage2d_tiles(g->n[0], g->n[1]) : isw::sweep3d_x_tiles(g->n);
 }
 
 // One RK3 step on stream s: the time step (when cfl > 0), then the three
 // stages, with the intermediate states in U1 and U2 (nc*N each), the
 // time-step words maxbits (two, zero on entry, left zero) and, for
-// fused_dt, the per-tile maxima in part (dt_slots).  With fused_dt the
-// first stage writes L(U) into U1 and its tiles' max wave speeds, one
-// workgroup turns those into dt, and the second stage reads U + dt L: the
-// same states, bit for bit, without a pass of its own over U.
+// fused_dt, the per-tile maxima in part (dt_slots).  With fused_dt in 2D
+// the first stage writes L(U) into U1 and its tiles' max wave speeds, one
+// workgroup turns those into dt, and the second stage reads U + dt L; in
+// 3D the first stage's x sweep stores the maxima and dt is formed before
+// its y sweep.  The same states, bit for bit, without a pass of its own
+// over U.
 hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o, double* U,
                        double* dt, isweno_stats* stats, double* U1, double* U2,
                        unsigned long long* maxbits, unsigned long long* part, bool timed,
                        hipStream_t s) {
   hipError_t e;
   const bool fused = fused_dt(g, o);
+  const bool fused2d = fused && g->ndim == 2;
   if (o->cfl > 0.0 && !fused) {
     KTimer t(timed ? c : nullptr, ISWENO_K_CFL);
     if ((e = isw::launch_cfl(g->ndim, U, g->n, g->dx, o->cfl, o->dt_max, maxbits, dt, c->ncu,
@@ -212,7 +243,7 @@ hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o
   isw::SweepArgs a = base_args(g, o, stats);
   a.dt = dt;
   a.U0 = U;
-  if (fused) {
+  if (fused2d) {
     // stage 1: L(U) into U1, the tiles' max wave speeds into part; dt
     a.Uin = U;
     a.Rout = U1;
@@ -230,10 +261,13 @@ hipError_t enqueue_rk3(isweno_ctx* c, const isweno_grid* g, const isweno_opts* o
     a.Uout = U2;
     if ((e = stage(c, g, o, a, U2, isw::OUT_RK2L, timed, s)) != hipSuccess) return e;
   } else {
-    // stage 1: U1 = U + dt L(U)
+    // stage 1: U1 = U + dt L(U) (3D with fused_dt: dt formed after its x sweep)
     a.Uin = U;
     a.Uout = U1;
-    if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, timed, s)) != hipSuccess) return e;
+    const DtInStage fin{part, dt_slots(g, o), o->cfl, o->dt_max, dt};
+    if ((e = stage(c, g, o, a, U1, isw::OUT_RK1, timed, s, fused ? &fin : nullptr)) !=
+        hipSuccess)
+      return e;
     // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1))
     a.Uin = U1;
     a.Uout = U2;

@@ -80,8 +80,19 @@ __global__ __launch_bounds__(kCflThreads) void cfl_kernel(
 __global__ __launch_bounds__(kCflThreads) void cfl_final_kernel(const unsigned long long* part,
                                                                  int64_t n, double cfl,
                                                                  double dt_max, double* dt) {
+  // eight loads in flight per lane (a 3D x sweep leaves tens of thousands)
+  constexpr int UNR = 8;
   unsigned long long b = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kCflThreads) b = part[i] > b ? part[i] : b;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kCflThreads * UNR) {
+    unsigned long long v[UNR];
+#pragma unroll
+    for (int r = 0; r < UNR; r++) {
+      const int64_t i = i0 + (int64_t)r * kCflThreads;
+      v[r] = i < n ? part[i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < UNR; r++) b = v[r] > b ? v[r] : b;
+  }
   __shared__ unsigned long long red[kCflThreads / 64];
   wave_max_bits(__longlong_as_double((long long)b), red);
   __syncthreads();
@@ -92,6 +103,11 @@ __global__ __launch_bounds__(kCflThreads) void cfl_final_kernel(const unsigned l
     if (dt_max > 0.0 && h > dt_max) h = dt_max;
     *dt = h;
   }
+}
+
+int64_t sweep3d_x_tiles(const int64_t* n) {
+  using TS = TileShape<3, 0>;
+  return ((n[0] + TS::TL - 1) / TS::TL) * ((n[1] * n[2] + TS::TW - 1) / TS::TW);
 }
 
 hipError_t launch_cfl_final(const unsigned long long* part, int64_t n, double cfl,

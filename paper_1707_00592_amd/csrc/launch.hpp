@@ -41,13 +41,17 @@ hipError_t launch_cfl(int ndim, const double* U, const int64_t* n, const double*
                       int ncu, hipStream_t s, LaunchEvents ev = {});
 
 // dt = cfl / max over n per-workgroup maxima (bits of positive doubles, as
-// the first fused 2D stage stores them), clipped to dt_max > 0; one
-// workgroup.
+// the first fused 2D stage or the first 3D sweep stores them), clipped to
+// dt_max > 0; one workgroup.
 hipError_t launch_cfl_final(const unsigned long long* part, int64_t n, double cfl,
                             double dt_max, double* dt, hipStream_t s, LaunchEvents ev = {});
 
 // The number of workgroups (tiles) of the fused 2D stage on an nx x ny grid.
 int64_t stage2d_tiles(int64_t nx, int64_t ny);
+
+// The number of workgroups (tiles) of a 3D x sweep on an n[0] x n[1] x n[2]
+// grid (one OUT_PARTIAL_S maximum each).
+int64_t sweep3d_x_tiles(const int64_t* n);
 
 // Zeroes the time-step words by a kernel (used instead of a
 // memset, which a captured graph should not contain).

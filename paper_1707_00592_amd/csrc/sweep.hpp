@@ -31,7 +31,9 @@ enum OutMode {
   OUT_RK3 = 4,      // Uout = 1/3 U0 + 2/3 (Uin + dt L)
   // the time step inside the first two stages (fused 2D stage only):
   OUT_RK1L = 5,     // Rout = L(Uin), and each workgroup's max wave speed of Uin
-  OUT_RK2L = 6      // as OUT_RK2 with the stage input U0 + dt R, R = L(U0) of OUT_RK1L
+  OUT_RK2L = 6,     // as OUT_RK2 with the stage input U0 + dt R, R = L(U0) of OUT_RK1L
+  // the time step inside the first sweep of a 3D stage:
+  OUT_PARTIAL_S = 7 // as OUT_PARTIAL (x sweep), and each workgroup's max wave speed of Uin
 };
 
 enum { ST_OK = 0, ST_NONPHYSICAL = -4 };
@@ -59,7 +61,8 @@ struct SweepArgs {
   const uint16_t* mlp; // packed bf16 network (learned weights only)
   float mlp_thr;
   unsigned long long* shortcut;  // 256 x 3 counters of shortcut field-sides, or null
-  // OUT_RK1L: one max wave speed per workgroup (the bits of the double)
+  // OUT_RK1L, OUT_PARTIAL_S: one max wave speed per workgroup (the bits of
+  // the double)
   unsigned long long* cflp;
 };
 

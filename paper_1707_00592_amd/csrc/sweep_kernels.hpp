@@ -61,7 +61,7 @@ struct Geo {
 
 template <typename T, int NDIM, int D, int TL, int TW, int NTHR, int MODE,
           bool READ_R, bool CUT>
-__global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
+__global__ __launch_bounds__(NTHR, MODE == OUT_PARTIAL_S ? 5 : 1) void sweep_kernel(SweepArgs g) {
   constexpr int NC = 4 + NDIM;
   constexpr int NP = TL + 6;     // staged positions along D
   constexpr int NF = TL + 1;     // faces along D per tile row
@@ -88,6 +88,10 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
   T* const sf = reinterpret_cast<T*>(lds + SF_OFF);
   __shared__ int s_status;
   __shared__ int s_skip;
+  // OUT_PARTIAL_S: this x sweep also finds its tile's max wave speed (the
+  // step's time step; the tiles of an x sweep hold every cell once)
+  constexpr bool SPEEDS = MODE == OUT_PARTIAL_S;
+  __shared__ unsigned long long s_red[SPEEDS ? NTHR / 64 : 1];
 
   const Geo<NDIM, D> geo(g.n);
   const int64_t ntl = (geo.nL + TL - 1) / TL;
@@ -106,7 +110,10 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     s_skip = g.stats ? (__atomic_load_n(&g.stats->status, __ATOMIC_RELAXED) != ST_OK) : 0;
   }
   __syncthreads();
-  if (s_skip) return;
+  if (s_skip) {
+    if (SPEEDS && tid == 0) g.cflp[blockIdx.x] = 0ull;
+    return;
+  }
 
   auto lidx = [](int c, int w, int p) {
     const int r = !ALIAS ? c : c >= NC - 2 ? c - (NC - 2) : c + 2;
@@ -118,6 +125,8 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
 
   // 1. stage primitives (FP64) with ghost cells
   bool bad = false;
+  double m = 0.0;  // SPEEDS: the lane's max wave speed
+  const double dxs[3] = {g.dx[0], g.dx[1], g.dx[2]};
   for (int e = tid; e < TW * NP; e += NTHR) {
     const int w = D == 0 ? e / NP : e % TW;
     const int p = D == 0 ? e % NP : e / TW;
@@ -129,13 +138,27 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
     const int64_t cell = a * geo.sA + li * geo.sL + tt * geo.sT;
     double q[NC];
     cell_prim<NDIM, T>(g.Uin, N, cell, q);
-    if (p >= 3 && p < 3 + TL && l < geo.nL) bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
+    if (p >= 3 && p < 3 + TL && l < geo.nL) {
+      bad = bad || !cell_ok<NDIM>(g.Uin, N, cell, q);
+      if constexpr (SPEEDS) {
+        const double sp = cell_speed<NDIM, T>(q, dxs);
+        m = (sp > m || sp != sp) ? sp : m;
+      }
+    }
     if (flip) q[1 + D] = -q[1 + D];
 #pragma unroll
     for (int c = 0; c < NC; c++) sq[lidx(c, w, p)] = T(q[c]);
   }
+  if constexpr (SPEEDS) wave_max_bits(m, s_red);
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
+  if constexpr (SPEEDS) {
+    if (tid == 0) {
+      unsigned long long b = s_red[0];
+      for (int w = 1; w < NTHR / 64; w++) b = s_red[w] > b ? s_red[w] : b;
+      g.cflp[blockIdx.x] = b;
+    }
+  }
 
   // 2. faces: thread tid owns face (w, j); with ALIAS the values wait in
   // registers until every face has read sq
@@ -216,7 +239,7 @@ __global__ __launch_bounds__(NTHR) void sweep_kernel(SweepArgs g) {
       }
       double L = READ_R ? g.R[kc * N + cell] + r : r;
       const int64_t o = kc * N + cell;
-      if (MODE == OUT_PARTIAL || MODE == OUT_RHS) {
+      if (MODE == OUT_PARTIAL || MODE == OUT_PARTIAL_S || MODE == OUT_RHS) {
         g.Rout[o] = L;
       } else {
         const double h = *g.dt;
@@ -454,6 +477,14 @@ static hipError_t launch_sweep_d(const SweepArgs& a, int mode, bool readR, hipSt
     case OUT_PARTIAL:
       return readR ? launch_sweep_t<T, NDIM, D, OUT_PARTIAL, true, LEARNED, CUT>(a, s, ev)
                    : launch_sweep_t<T, NDIM, D, OUT_PARTIAL, false, LEARNED, CUT>(a, s, ev);
+    case OUT_PARTIAL_S:
+      // the first sweep of a 3D stage, also storing its tiles' max wave speeds
+      if constexpr (NDIM == 3 && D == 0 && !LEARNED) {
+        if (readR || !a.cflp) return hipErrorInvalidValue;
+        return launch_sweep_t<T, NDIM, D, OUT_PARTIAL_S, false, LEARNED, CUT>(a, s, ev);
+      } else {
+        return hipErrorInvalidValue;
+      }
     case OUT_RHS:
       return readR ? launch_sweep_t<T, NDIM, D, OUT_RHS, true, LEARNED, CUT>(a, s, ev)
                    : launch_sweep_t<T, NDIM, D, OUT_RHS, false, LEARNED, CUT>(a, s, ev);

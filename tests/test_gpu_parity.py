@@ -168,20 +168,23 @@ def test_cfl_dt_matches_oracle(lib, ctx):
 
 
 def test_time_step_inside_the_first_stage(lib, ctx):
-    """A CFL step of a 2D grid forms its time step inside the first stage
-    (each tile's max wave speed of U^n, then one workgroup); dt must equal the
-    standalone reduction's and the oracle's bit for bit, and the step's state
-    the oracle's.  Grids with tile counts that are not multiples of 8, tiles
-    that hold only a few cells, reflective and periodic ends, both weight
-    forms and both MOOD forms; the float form's dt within 4 ulp."""
+    """A CFL step of a 2D or 3D grid forms its time step inside the first
+    stage (2D: each tile's max wave speed of U^n in the fused stage; 3D: in
+    the x sweep; then one workgroup); dt must equal the standalone
+    reduction's and the oracle's bit for bit, and the step's state the
+    oracle's.  Grids with tile counts that are not multiples of 8, tiles that
+    hold only a few cells, reflective and periodic ends, both weight forms
+    and both MOOD forms; the float form's dt within 4 ulp."""
     torch = _torch()
     cases = [((150, 70), 1, "transmissive"), ((16, 16), 2, "reflective"),
-             ((31, 33), 3, "periodic"), ((1, 40), 4, "periodic"), ((47, 1), 5, "transmissive")]
+             ((31, 33), 3, "periodic"), ((1, 40), 4, "periodic"), ((47, 1), 5, "transmissive"),
+             ((20, 18, 17), 6, "reflective"), ((33, 9, 5), 7, "periodic"), ((1, 16, 9), 8, "transmissive")]
     for shape, seed, bc in cases:
         p = wl.random_two_phase(shape, seed=seed)
         b = {"transmissive": 0, "periodic": 1, "reflective": 2}[bc]
-        og = oracle.make_grid(p.n, p.dx, [b, b], [b, b])
-        ig = lib.make_grid(p.n, p.dx, [b, b], [b, b])
+        nd = len(shape)
+        og = oracle.make_grid(p.n, p.dx, [b] * nd, [b] * nd)
+        ig = lib.make_grid(p.n, p.dx, [b] * nd, [b] * nd)
         for weights in (lib.W_MODIFIED, lib.W_CUTOFF):
             for mood in (True, lib.MOOD_GATHER):
                 oo = oracle.make_opts(weights=weights, mood=True, cfl=0.5)
