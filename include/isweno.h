@@ -191,9 +191,9 @@ ISWENO_API int isweno_cfl_dt(isweno_ctx *ctx, const isweno_grid *grid,
  *   U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
  *   U^{n+1} = 1/3 U + 2/3 (U2 + dt L(U2)).
  * dt is a device scalar: computed from U^n and written when opts->cfl > 0
- * (the value of isweno_cfl_dt on U^n; in the FP32 form of a 2D grid within
- * a few ulp of it, its primitive recovery dividing through reciprocals),
- * read otherwise.  The step's launches are captured once into a HIP graph
+ * (the value of isweno_cfl_dt on U^n; in the FP32 form of a 2D or 3D grid
+ * within a few ulp of it, its primitive recovery dividing through
+ * reciprocals), read otherwise.  The step's launches are captured once into a HIP graph
  * per (U, dt, stats, grid, opts) and replayed on the given stream; with
  * kernel timing enabled, or with opts->dt_max > 0, they are launched
  * directly instead.  Same results either way. */
@@ -209,11 +209,11 @@ ISWENO_API int isweno_rk3_step(isweno_ctx *ctx, const isweno_grid *grid,
  * until the process ends) instead of the context's workspace, and it
  * launches its kernels directly (no graph, no timing events).  It calls no
  * hipMalloc, hipFree or other allocating routine.
- *   - Limit: (2 * nc * N + T) * 8 bytes <= 128 MiB, T the number of
- *     15 x 16 tiles of a 2D grid stepped with cfl > 0 (else 0) (2D, nc = 6:
- *     N up to about 1,397,600 cells; 3D, nc = 7: N <= 1,198,372); larger
- *     grids return ISWENO_ERR_ARG and enqueue nothing.  Other errors as
- *     isweno_rk3_step.
+ *   - Limit: (2 * nc * N + T) * 8 bytes <= 128 MiB, T the number of tiles
+ *     whose wave speeds a step with cfl > 0 keeps (2D: 15 x 16 cells; 3D:
+ *     31 x 8 cells of x lines; else 0) (2D, nc = 6: N up to about 1,397,600
+ *     cells; 3D, nc = 7: N up to about 1,197,900); larger grids return
+ *     ISWENO_ERR_ARG and enqueue nothing.  Other errors as isweno_rk3_step.
  *   - The scratch is shared by every call on one GPU and keeps the last
  *     call's contents; the step clears what must start at zero.  Calls that
  *     overlap on one GPU (other streams, other contexts, other host threads)
