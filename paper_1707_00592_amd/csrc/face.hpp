@@ -332,8 +332,7 @@ __device__ __forceinline__ float weno_f32(float a, float b, float c, float d,
 // sum, so that a stencil set with nothing cut gives d_k exactly.  Order 3
 // cuts among the two 2-point stencils.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double cut_share_f64(double g, double gm) {
-  const double t = g / gm;
+__device__ __forceinline__ double cut_pow6(double t) {
   const double t2 = t * t;
   return (t2 * t2) * t2;
 }
@@ -356,35 +355,9 @@ constexpr CutWeights make_cut_weights() {
 }
 __constant__ CutWeights kCutWeights = make_cut_weights();
 
-__device__ __forceinline__ double weno_f64_cutoff(double a, double b, double c, double d,
-                                                  double e, double eps, bool order3,
-                                                  int& nlin) {
-  int mask = 15;
-  if (eps > 0.0 && tau5<double>(a, b, c, d, e) == 0.0) {
-    // every ratio is zero: no stencil is cut
-    nlin++;
-  } else {
-    const Ind<double> s = indicators<double>(a, b, c, d, e);
-    const double r12 = s.tau / (s.b12 + eps);
-    const double g1 = 1.0 + (s.tau / (s.b1 + eps)) * r12;
-    const double g2 = 1.0 + (s.tau / (s.b2 + eps)) * r12;
-    double gm = g1;
-    if (g2 > gm) gm = g2;
-    if (order3) {
-      const double p1 = cut_share_f64(g1, gm), p2 = cut_share_f64(g2, gm);
-      const double th = ISW_CT * (p1 + p2);
-      mask = (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0);
-    } else {
-      const double g3 = 1.0 + s.tau / (s.b3 + eps);
-      const double g4 = 1.0 + s.tau / (s.b4 + eps);
-      if (g3 > gm) gm = g3;
-      if (g4 > gm) gm = g4;
-      const double p1 = cut_share_f64(g1, gm), p2 = cut_share_f64(g2, gm),
-                   p3 = cut_share_f64(g3, gm), p4 = cut_share_f64(g4, gm);
-      const double th = ISW_CT * (((p1 + p2) + p3) + p4);
-      mask = (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0) | (p3 >= th ? 4 : 0) | (p4 >= th ? 8 : 0);
-    }
-  }
+// Eq. (19) with the weights of a kept-stencil mask.
+__device__ __forceinline__ double cut_combine(int mask, double a, double b, double c, double d,
+                                              double e, bool order3) {
   if (order3) mask &= 3;
   const double* w = kCutWeights.w[mask];
   const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
@@ -393,6 +366,72 @@ __device__ __forceinline__ double weno_f64_cutoff(double a, double b, double c, 
   const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
   const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
   return ((w[0] * c1 + w[1] * c2) + w[2] * c3) + w[3] * c4;
+}
+
+// The kept-stencil mask of the share test.  FAST: every quotient through the
+// unscaled division sequence (divide, recip), the shares t_k = g_k / g_max
+// through one reciprocal of g_max.  Inside the range of fast_division_range
+// with epsilon in [2^-200, 2^100], each ratio tau/(beta + eps) is one of the
+// WENO-IS weights' quotients, g_k = 1 + ratios lies in [1, 2^801] and
+// t_k = g_k / g_max in [2^-801, 1]: no operand scaling, no special value,
+// the bits of the plain divisions.  Otherwise: the plain divisions.
+template <bool FAST>
+__device__ __forceinline__ double cut_quot(double x, double y) {
+  if constexpr (FAST) return divide(x, recip(y));
+  else return x / y;
+}
+
+template <bool FAST>
+__device__ __forceinline__ int cut_mask_f64(const Ind<double>& s, double eps, bool order3) {
+  const double r12 = cut_quot<FAST>(s.tau, s.b12 + eps);
+  const double g1 = 1.0 + cut_quot<FAST>(s.tau, s.b1 + eps) * r12;
+  const double g2 = 1.0 + cut_quot<FAST>(s.tau, s.b2 + eps) * r12;
+  double gm = g1;
+  if (g2 > gm) gm = g2;
+  if (order3) {
+    const Recip rg = recip(gm);
+    const double p1 = cut_pow6(FAST ? divide(g1, rg) : g1 / gm);
+    const double p2 = cut_pow6(FAST ? divide(g2, rg) : g2 / gm);
+    const double th = ISW_CT * (p1 + p2);
+    return (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0);
+  }
+  const double g3 = 1.0 + cut_quot<FAST>(s.tau, s.b3 + eps);
+  const double g4 = 1.0 + cut_quot<FAST>(s.tau, s.b4 + eps);
+  if (g3 > gm) gm = g3;
+  if (g4 > gm) gm = g4;
+  const Recip rg = recip(gm);
+  const double p1 = cut_pow6(FAST ? divide(g1, rg) : g1 / gm);
+  const double p2 = cut_pow6(FAST ? divide(g2, rg) : g2 / gm);
+  const double p3 = cut_pow6(FAST ? divide(g3, rg) : g3 / gm);
+  const double p4 = cut_pow6(FAST ? divide(g4, rg) : g4 / gm);
+  const double th = ISW_CT * (((p1 + p2) + p3) + p4);
+  return (p1 >= th ? 1 : 0) | (p2 >= th ? 2 : 0) | (p3 >= th ? 4 : 0) | (p4 >= th ? 8 : 0);
+}
+
+// FP64 cut-off reconstruction as used by the kernels.  Stencils with
+// tau5 = 0 keep every stencil (every ratio is zero) and take the weights of
+// the full set as compile-time constants.  The others take the FAST mask;
+// lanes outside its range redo the whole reconstruction with the plain
+// divisions (a separate path, as in weno_f64_fast, keeps the common path's
+// registers low).
+__device__ __forceinline__ double weno_f64_cutoff(double a, double b, double c, double d,
+                                                  double e, double eps, bool order3,
+                                                  int& nlin) {
+  if (eps > 0.0 && tau5<double>(a, b, c, d, e) == 0.0) {
+    nlin++;
+    constexpr CutWeights W = make_cut_weights();
+    const double c1 = (1.0 / 2.0) * c + (1.0 / 2.0) * d;
+    const double c2 = -(1.0 / 2.0) * b + (3.0 / 2.0) * c;
+    if (order3) return W.w[3][0] * c1 + W.w[3][1] * c2;
+    const double c3 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e;
+    const double c4 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c;
+    return ((W.w[15][0] * c1 + W.w[15][1] * c2) + W.w[15][2] * c3) + W.w[15][3] * c4;
+  }
+  const Ind<double> s = indicators<double>(a, b, c, d, e);
+  double q = cut_combine(cut_mask_f64<true>(s, eps, order3), a, b, c, d, e, order3);
+  if (!(eps >= 0x1p-200 && eps <= 0x1p100 && fast_division_range(s)))
+    q = cut_combine(cut_mask_f64<false>(s, eps, order3), a, b, c, d, e, order3);
+  return q;
 }
 
 // The same cut-off in the float form: the stencil shifted and scaled as in

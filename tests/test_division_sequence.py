@@ -6,8 +6,9 @@ it bit for bit (the oracle divides plainly):
     scaling and special-value fix-up -- the hardware reciprocal r0 of y, two
     Newton steps r += r (1 - y r), q = x r, one residual correction
     q += r (x - y q), every step a fused multiply-add -- used where y and x
-    lie in the checked range of the WENO-IS weights, sharing one reciprocal
-    among the quotients by the same denominator;
+    lie in the checked range of the WENO-IS weights (and of the cut-off
+    weights' share test), sharing one reciprocal among the quotients by the
+    same denominator;
   * star_zeros(): the signed zero 0 * (num / den) of eq. (14)'s discarded
     star state, formed as (0 * num) * den without the division.
 With the hardware reciprocal, divide() runs the very instructions of the
@@ -97,6 +98,15 @@ def _cases(rs):
         a = s * rs.uniform(0.0, 1.0)
         if a >= 0.1:
             cases.append((a, s))
+    # cut-off weights' share test in the same checked range: the shares
+    # t_k = g_k / g_max with 1 <= g_k <= g_max <= 2^801 (g = 1 + ratios),
+    # among them t = 1 exactly
+    for _ in range(300):
+        gm = abs(_rand(rs, 0, 800))
+        g = max(1.0, gm * rs.uniform(0.0, 1.0))
+        cases.append((g, gm))
+    for gm in (1.0, math.ldexp(2.0 - 2.0 ** -52, 800), math.ldexp(1.0, 800), 3.0):
+        cases += [(gm, gm), (1.0, gm)]
     # reciprocals with all-ones or power-of-two mantissas, quotients next to
     # a power of two
     for e in (-100, -37, 0, 51, 99):
