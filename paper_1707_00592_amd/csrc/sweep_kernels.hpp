@@ -59,6 +59,20 @@ struct Geo {
   }
 };
 
+// Tile of workgroup b among ntiles.  Workgroups go to the 8 XCDs in turn
+// (b mod 8), each XCD with its own L2; tiles are numbered with the sweep
+// axis fastest, so consecutive tiles share halo lines.  Each XCD takes runs
+// of kSweepRun consecutive tiles, the runs of the 8 XCDs interleaved (the
+// work of a front stays spread over the XCDs); tiles past the last whole
+// group of 8 runs keep their own number.  A bijection of [0, ntiles).
+constexpr int64_t kSweepRun = 64;
+__device__ __forceinline__ int64_t sweep_tile(int64_t b, int64_t ntiles) {
+  const int64_t whole = ntiles / (8 * kSweepRun) * (8 * kSweepRun);
+  if (b >= whole) return b;
+  const int64_t xcd = b & 7, k = b >> 3;
+  return ((k / kSweepRun) * 8 + xcd) * kSweepRun + k % kSweepRun;
+}
+
 template <typename T, int NDIM, int D, int TL, int TW, int NTHR, int MODE,
           bool READ_R, bool CUT>
 __global__ __launch_bounds__(NTHR, MODE == OUT_PARTIAL_S ? 5 : 1) void sweep_kernel(SweepArgs g) {
@@ -95,10 +109,10 @@ __global__ __launch_bounds__(NTHR, MODE == OUT_PARTIAL_S ? 5 : 1) void sweep_ker
 
   const Geo<NDIM, D> geo(g.n);
   const int64_t ntl = (geo.nL + TL - 1) / TL;
-  const int64_t bid = blockIdx.x;
+  const int64_t nta = (geo.nA + TW - 1) / TW;
+  const int64_t bid = sweep_tile(blockIdx.x, ntl * nta * geo.nT);
   const int64_t tl = bid % ntl;
   const int64_t rest = bid / ntl;
-  const int64_t nta = (geo.nA + TW - 1) / TW;
   const int64_t ta = rest % nta;
   const int64_t tt = rest / nta;
   const int64_t l0 = tl * TL, a0 = ta * TW;
