@@ -246,7 +246,10 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
       storey(tid, G, vs);
     }
   }
-  __syncthreads();
+  // The x faces read only the staged primitives; the y faces' values are
+  // read by the cells, after the barrier below.  The gathered cascade
+  // reuses its queue in the x phase, so it waits here.
+  if constexpr (GATHER) __syncthreads();
 
   // 3. x faces: lane tid holds face (cx, cy), between cells cx-1 and cx of
   // row cy, and, for cx < 15, cell (cx, cy)
@@ -315,6 +318,9 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
         atomicAdd(&g.shortcut[(blk & 255) * 3 + d], (unsigned long long)ws);
     }
   }
+  // every y face is in sfy from here on (a wave that finished its y faces
+  // early went on to its x face first)
+  if constexpr (!GATHER) __syncthreads();
   // the face to the right of cell cx is the next lane's (same 16-lane
   // group); for cx = 15 there is no cell and the value goes unused
   double Fr[NC];
