@@ -73,8 +73,8 @@ PEAK = {"f64_valu_tflops": 78.6, "f32_valu_tflops": 157.3, "hbm_gbs": 8000.0}
 VALU_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STAGE_SOURCES = ("face.hpp", "sweep.hpp", "sweep_kernels.hpp", "kernels.hip", "stage2d_kernel.hpp",
-                 "stage2d.hip", "stage2d_f32.hip")
+STAGE_SOURCES = ("face.hpp", "sweep.hpp", "sweep_kernels.hpp", "kernels.hip", "sweep_f32.hip",
+                 "stage2d_kernel.hpp", "stage2d.hip", "stage2d_f32.hip")
 COUNTERS_FILE = os.path.join(HERE, "profiles", "stage_2d_shock_bubble_1024x512_counters.md")
 COUNTERS_3D = os.path.join(HERE, "profiles", "sweep_3d_shock_droplet_256_counters.md")
 

@@ -3,8 +3,9 @@
 Every source under csrc/ is compiled with hipcc for gfx950 only, with
 packed FP32 instructions disabled and fused multiply-add contraction off
 (the FP64 path is written in one fixed operation order), except the float
-form's 2D stage (stage2d_f32.hip), which is held to an error bound and is
-built with contraction on.
+form's 2D stage, sweeps and batched kernels (stage2d_f32.hip, sweep_f32.hip,
+batch_f32.hip), which are held to an error bound and are built with
+contraction on.
 """
 from __future__ import annotations
 
@@ -22,10 +23,10 @@ LIB = BUILD / "libisweno.so"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "sweep_cut.hip", "stage2d.hip", "stage2d_f32.hip", "batch.hip",
-           "mlp.hip", "api.hip"]
+SOURCES = ["kernels.hip", "sweep_f32.hip", "sweep_cut.hip", "stage2d.hip", "stage2d_f32.hip",
+           "batch.hip", "batch_f32.hip", "mlp.hip", "api.hip"]
 # sources whose arithmetic is held to an error bound, not to the oracle's bits
-CONTRACTED = {"stage2d_f32.hip"}
+CONTRACTED = {"stage2d_f32.hip", "sweep_f32.hip", "batch_f32.hip"}
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -131,7 +131,7 @@ hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int 
   // the cut-off weights run in kernels of their own (another translation
   // unit), so that the other forms keep their register allocation
   if (a.weights == W_CUTOFF) return launch_sweep_cut(precision, ndim, D, a, mode, readR, s, ev);
-  return precision == 1 ? launch_sweep_p<float, false, false>(ndim, D, a, mode, readR, s, ev)
+  return precision == 1 ? launch_sweep_f32(ndim, D, a, mode, readR, s, ev)
                         : launch_sweep_p<double, false, false>(ndim, D, a, mode, readR, s, ev);
 }
 
