@@ -36,6 +36,8 @@ hipError_t launch_sweep_f32(int ndim, int D, const SweepArgs& a, int mode, bool 
                             hipStream_t s, LaunchEvents ev);
 hipError_t launch_sweep_mlp(int ndim, int D, const SweepArgs& a, int mode, bool readR,
                             hipStream_t s, LaunchEvents ev);
+hipError_t launch_sweep_cut_f32(int ndim, int D, const SweepArgs& a, int mode, bool readR,
+                                hipStream_t s, LaunchEvents ev);
 
 // Bytes of the time-step words (the max and the ticket).
 constexpr size_t kCflWordsBytes = 256;
