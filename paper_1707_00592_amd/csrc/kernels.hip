@@ -126,7 +126,7 @@ hipError_t launch_sweep(int precision, int ndim, int D, const SweepArgs& a, int 
   if (a.weights == W_MLP) {
     // learned weights: float32 reconstruction with a packed network only
     if (precision != 1 || !a.mlp) return hipErrorInvalidValue;
-    return launch_sweep_mlp(ndim, D, a, mode, readR, s, ev);
+    return launch_sweep_p<float, true, false>(ndim, D, a, mode, readR, s, ev);
   }
   // the cut-off weights run in kernels of their own (another translation
   // unit), so that the other forms keep their register allocation

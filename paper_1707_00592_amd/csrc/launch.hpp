@@ -34,8 +34,6 @@ hipError_t launch_stage2d(int precision, const SweepArgs& a, int mode, hipStream
 hipError_t launch_stage2d_f32(const SweepArgs& a, int mode, hipStream_t s, LaunchEvents ev);
 hipError_t launch_sweep_f32(int ndim, int D, const SweepArgs& a, int mode, bool readR,
                             hipStream_t s, LaunchEvents ev);
-hipError_t launch_sweep_mlp(int ndim, int D, const SweepArgs& a, int mode, bool readR,
-                            hipStream_t s, LaunchEvents ev);
 hipError_t launch_sweep_cut_f32(int ndim, int D, const SweepArgs& a, int mode, bool readR,
                                 hipStream_t s, LaunchEvents ev);
 
