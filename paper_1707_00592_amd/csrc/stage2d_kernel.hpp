@@ -113,6 +113,11 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
     return;
   }
 
+  // The waves of a workgroup that is staging its tile run at a raised
+  // instruction priority (s_setprio), so that its loads are issued ahead of
+  // the arithmetic of the resident workgroups and arrive while they compute;
+  // back to normal once the tile is staged.
+  __builtin_amdgcn_s_setprio(1);
   // 1. stage primitives: the tile's interior cells, its rows extended by 3
   // cells each way along x and its columns by 3 each way along y
   bool bad = false;
@@ -156,6 +161,7 @@ __global__ __launch_bounds__(kThreads, CUT && GATHER ? 2 : 4) void stage2d_kerne
   if constexpr (SPEEDS) wave_max_bits(m, s_red);
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
   if (g.stats && tid == 0 && s_status != ST_OK) atomicExch(&g.stats->status, s_status);
   if constexpr (SPEEDS) {
     if (tid == 0) {

@@ -137,6 +137,10 @@ __global__ __launch_bounds__(NTHR, MODE == OUT_PARTIAL_S ? 5 : 1) void sweep_ker
     return D == 0 ? (k * TW + w) * NF + j : (k * NF + j) * TW + w;
   };
 
+  // FP64: raised instruction priority while the tile is staged (its loads
+  // go out ahead of the resident workgroups' arithmetic), normal afterwards
+  // (the float sweeps ran slower with it)
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
   // 1. stage primitives (FP64) with ghost cells
   bool bad = false;
   double m = 0.0;  // SPEEDS: the lane's max wave speed
@@ -166,6 +170,7 @@ __global__ __launch_bounds__(NTHR, MODE == OUT_PARTIAL_S ? 5 : 1) void sweep_ker
   if constexpr (SPEEDS) wave_max_bits(m, s_red);
   if (bad) s_status = ST_NONPHYSICAL;
   __syncthreads();
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(0);
   if constexpr (SPEEDS) {
     if (tid == 0) {
       unsigned long long b = s_red[0];
