@@ -64,6 +64,9 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
     const int64_t l0 = g.tstart[t] - lo;
     const int len = (int)((n - l0) < TL ? (n - l0) : TL);
     bool bad = false;
+    // FP64: raised instruction priority while the tile is staged (its loads
+    // go out ahead of the other workgroups' arithmetic), normal afterwards
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
     for (int p = tid; p < NP; p += NTHR) {
       const int64_t l = l0 + p - 3;
       if (l >= n + 3) continue;
@@ -81,6 +84,7 @@ __global__ __launch_bounds__(TL + 1) void batch_stage_kernel(BatchArgs g) {
       atomicExch(&g.pstatus[prob], (int32_t)ST_NONPHYSICAL);
     }
     __syncthreads();
+    if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(0);
     for (int j = tid; j <= len; j += NTHR) {
       Lds1<T> st;
       st.base = &sq[j];
